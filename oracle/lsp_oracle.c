@@ -1,0 +1,310 @@
+/*
+ * lsp_oracle.c -- plain, slow, FP64 reference for the normalized
+ * Lomb-Scargle periodogram.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is compiled into its own shared
+ * library (liblsp_oracle.so) and may be loaded only by the test suite, by
+ * the smoke check of the package entry point, and by the CPU-baseline leg
+ * of the benchmark.  It shares no code, header, table or helper with the
+ * HIP implementation in paper_1007_1658_amd/csrc, and nothing in the
+ * product path may call it.
+ *
+ * What it computes (Townsend, "Fast Calculation of the Lomb-Scargle
+ * Periodogram Using Graphics Processing Units"):
+ *
+ *   - Section 3, opening paragraph: the series is shifted and scaled to zero
+ *     mean and unit variance before the periodogram is formed.  Reading
+ *     taken here: population variance (divide by Nt).
+ *   - Eq. (2): the time offset tau from tan(2 w tau) = sum sin(2 w t_j) /
+ *     sum cos(2 w t_j), w = 2 pi f.  The atan2 branch is taken, with
+ *     atan2(0, 0) := 0 (the periodogram does not depend on the branch).
+ *   - Eq. (1): Pn(f) = 1/2 { [sum X_j cos w(t_j - tau)]^2 / sum cos^2 w(t_j - tau)
+ *                          + [sum X_j sin w(t_j - tau)]^2 / sum sin^2 w(t_j - tau) }.
+ *     A term whose denominator is <= 1e-12 * Nt is taken as 0 (its numerator
+ *     vanishes with it: f = 0, or the Nyquist frequency of even sampling).
+ *   - The evaluation is the direct one that Section 3 sets against its
+ *     refactoring: one pass over the series for the Eq. (2) sums, then a
+ *     second pass for the Eq. (1) sums.  It deliberately does NOT use the
+ *     single-pass form of Eqs. (5)-(8), which is what the GPU path computes.
+ *   - Eq. (3): the false-alarm probability
+ *         Q = 1 - [1 - (1 - 2 Pn / Nt)^((Nt - 3)/2)]^Nf,
+ *     evaluated through log1p/expm1 so that tiny Q keep their precision.
+ *
+ * The frequency grid is f_k = f_min + k * df (k = 0 .. Nf-1), formed from k
+ * directly; Eq. (9) of Section 4.3 is the case f_min = df.
+ *
+ * Phases are reduced in revolutions: p = f t_j, phi_j = p - nearbyint(p),
+ * using the raw times (no epoch shift), so that invariance under a time
+ * shift is a genuine test of both implementations.
+ *
+ * Every sum uses Neumaier's compensated summation.  Frequencies are spread
+ * over OpenMP threads; each frequency is computed by one thread in a fixed
+ * order, so the result does not depend on the thread count.
+ *
+ * A long-double twin of the periodogram exists only to pin the FP64 phase
+ * arithmetic of this oracle on long, epoch-offset baselines.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdlib.h>
+#include <stdint.h>
+#include <omp.h>
+
+#define ORACLE_OK 0
+#define ORACLE_ERR_ARG (-1)
+#define ORACLE_ERR_ZERO_VARIANCE (-2)
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+static const long double TWO_PI_L = 6.283185307179586476925286766559005768L;
+
+/* ---- Neumaier compensated summation ------------------------------------ */
+
+typedef struct { double s, c; } nsum;
+
+static void nsum_add(nsum *a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double nsum_get(const nsum *a) { return a->s + a->c; }
+
+typedef struct { long double s, c; } nsuml;
+
+static void nsuml_add(nsuml *a, long double v)
+{
+    long double t = a->s + v;
+    if (fabsl(a->s) >= fabsl(v))
+        a->c += (a->s - t) + v;
+    else
+        a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static long double nsuml_get(const nsuml *a) { return a->s + a->c; }
+
+/* ---- normalization (Section 3, opening paragraph) ----------------------- */
+
+/* X_j = (x_j - mean) / sigma with sigma^2 = (1/Nt) sum (x_j - mean)^2.
+   Returns ORACLE_ERR_ZERO_VARIANCE when every x_j is the same. */
+int oracle_normalize(const double *x, int64_t Nt, double *X,
+                     double *mean_out, double *var_out)
+{
+    if (!x || !X || Nt < 1)
+        return ORACLE_ERR_ARG;
+    nsum s = {0.0, 0.0};
+    for (int64_t j = 0; j < Nt; ++j)
+        nsum_add(&s, x[j]);
+    double mean = nsum_get(&s) / (double)Nt;
+    nsum v = {0.0, 0.0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        double d = x[j] - mean;
+        nsum_add(&v, d * d);
+    }
+    double var = nsum_get(&v) / (double)Nt;
+    if (mean_out) *mean_out = mean;
+    if (var_out) *var_out = var;
+    if (!(var > 0.0))
+        return ORACLE_ERR_ZERO_VARIANCE;
+    double inv_sigma = 1.0 / sqrt(var);
+    for (int64_t j = 0; j < Nt; ++j)
+        X[j] = (x[j] - mean) * inv_sigma;
+    return ORACLE_OK;
+}
+
+/* ---- Eqs. (1)-(2), two passes, one frequency ---------------------------- */
+
+static double pn_one_frequency(const double *t, const double *X, int64_t Nt,
+                               double f)
+{
+    /* pass 1, Eq. (2): S2 = sum sin 2wt_j, C2 = sum cos 2wt_j.
+       With phi_j = frac-to-nearest(f t_j) in revolutions, 2 w t_j = 4 pi phi_j
+       modulo 2 pi. */
+    nsum S2 = {0, 0}, C2 = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        double p = f * t[j];
+        double phi = p - nearbyint(p);
+        nsum_add(&S2, sin(2.0 * TWO_PI * phi));
+        nsum_add(&C2, cos(2.0 * TWO_PI * phi));
+    }
+    double s2 = nsum_get(&S2), c2 = nsum_get(&C2);
+    /* w tau in revolutions: psi = atan2(S2, C2) / (4 pi); atan2(0,0) = 0 */
+    double psi = (s2 == 0.0 && c2 == 0.0) ? 0.0 : atan2(s2, c2) / (2.0 * TWO_PI);
+
+    /* pass 2, Eq. (1): argument a_j = w (t_j - tau) = 2 pi (phi_j - psi) */
+    nsum YC = {0, 0}, YS = {0, 0}, DC = {0, 0}, DS = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        double p = f * t[j];
+        double phi = p - nearbyint(p);
+        double a = TWO_PI * (phi - psi);
+        double ca = cos(a), sa = sin(a);
+        nsum_add(&YC, X[j] * ca);
+        nsum_add(&YS, X[j] * sa);
+        nsum_add(&DC, ca * ca);
+        nsum_add(&DS, sa * sa);
+    }
+    double yc = nsum_get(&YC), ys = nsum_get(&YS);
+    double dc = nsum_get(&DC), ds = nsum_get(&DS);
+    double floor_d = 1e-12 * (double)Nt;
+    double pc = (dc > floor_d) ? yc * yc / dc : 0.0;
+    double ps = (ds > floor_d) ? ys * ys / ds : 0.0;
+    return 0.5 * (pc + ps);
+}
+
+static long double pn_one_frequency_l(const long double *t, const long double *X,
+                                      int64_t Nt, long double f)
+{
+    nsuml S2 = {0, 0}, C2 = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        long double p = f * t[j];
+        long double phi = p - nearbyintl(p);
+        nsuml_add(&S2, sinl(2.0L * TWO_PI_L * phi));
+        nsuml_add(&C2, cosl(2.0L * TWO_PI_L * phi));
+    }
+    long double s2 = nsuml_get(&S2), c2 = nsuml_get(&C2);
+    long double psi = (s2 == 0.0L && c2 == 0.0L) ? 0.0L
+                                                 : atan2l(s2, c2) / (2.0L * TWO_PI_L);
+    nsuml YC = {0, 0}, YS = {0, 0}, DC = {0, 0}, DS = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        long double p = f * t[j];
+        long double phi = p - nearbyintl(p);
+        long double a = TWO_PI_L * (phi - psi);
+        long double ca = cosl(a), sa = sinl(a);
+        nsuml_add(&YC, X[j] * ca);
+        nsuml_add(&YS, X[j] * sa);
+        nsuml_add(&DC, ca * ca);
+        nsuml_add(&DS, sa * sa);
+    }
+    long double yc = nsuml_get(&YC), ys = nsuml_get(&YS);
+    long double dc = nsuml_get(&DC), ds = nsuml_get(&DS);
+    long double floor_d = 1e-12L * (long double)Nt;
+    long double pc = (dc > floor_d) ? yc * yc / dc : 0.0L;
+    long double ps = (ds > floor_d) ? ys * ys / ds : 0.0L;
+    return 0.5L * (pc + ps);
+}
+
+/* ---- public entry points ------------------------------------------------ */
+
+/* Pn at f_k = f_min + k df.  When klist is NULL, k = 0..n_out-1 and Pn has
+   n_out entries; otherwise Pn[i] is the value at k = klist[i].
+   x is the raw series (normalized here).  nthreads <= 0: OpenMP default. */
+int oracle_periodogram(const double *t, const double *x, int64_t Nt,
+                       double f_min, double df, const int64_t *klist,
+                       int64_t n_out, double *Pn, int nthreads)
+{
+    if (!t || !x || !Pn || Nt < 2 || n_out < 0 || !isfinite(f_min) ||
+        !isfinite(df))
+        return ORACLE_ERR_ARG;
+    double *X = (double *)malloc((size_t)Nt * sizeof(double));
+    if (!X)
+        return ORACLE_ERR_ARG;
+    int rc = oracle_normalize(x, Nt, X, NULL, NULL);
+    if (rc != ORACLE_OK) {
+        free(X);
+        return rc;
+    }
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t i = 0; i < n_out; ++i) {
+        int64_t k = klist ? klist[i] : i;
+        double f = f_min + (double)k * df;
+        Pn[i] = pn_one_frequency(t, X, Nt, f);
+    }
+    free(X);
+    return ORACLE_OK;
+}
+
+/* Same as oracle_periodogram, carried out in 80-bit long double (times,
+   normalization, phases, trigonometry and sums).  Output rounded to double. */
+int oracle_periodogram_ld(const double *t, const double *x, int64_t Nt,
+                          double f_min, double df, const int64_t *klist,
+                          int64_t n_out, double *Pn, int nthreads)
+{
+    if (!t || !x || !Pn || Nt < 2 || n_out < 0 || !isfinite(f_min) ||
+        !isfinite(df))
+        return ORACLE_ERR_ARG;
+    long double *T = (long double *)malloc((size_t)Nt * sizeof(long double));
+    long double *X = (long double *)malloc((size_t)Nt * sizeof(long double));
+    if (!T || !X) {
+        free(T);
+        free(X);
+        return ORACLE_ERR_ARG;
+    }
+    nsuml s = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j)
+        nsuml_add(&s, (long double)x[j]);
+    long double mean = nsuml_get(&s) / (long double)Nt;
+    nsuml v = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        long double d = (long double)x[j] - mean;
+        nsuml_add(&v, d * d);
+    }
+    long double var = nsuml_get(&v) / (long double)Nt;
+    if (!(var > 0.0L)) {
+        free(T);
+        free(X);
+        return ORACLE_ERR_ZERO_VARIANCE;
+    }
+    long double inv_sigma = 1.0L / sqrtl(var);
+    for (int64_t j = 0; j < Nt; ++j) {
+        T[j] = (long double)t[j];
+        X[j] = ((long double)x[j] - mean) * inv_sigma;
+    }
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 4) num_threads(nthreads)
+    for (int64_t i = 0; i < n_out; ++i) {
+        int64_t k = klist ? klist[i] : i;
+        long double f = (long double)f_min + (long double)k * (long double)df;
+        Pn[i] = (double)pn_one_frequency_l(T, X, Nt, f);
+    }
+    free(T);
+    free(X);
+    return ORACLE_OK;
+}
+
+/* Eq. (3): Q = 1 - [1 - (1 - 2Pn/Nt)^((Nt-3)/2)]^Nf, for Nt >= 4, Nf >= 1.
+   Returns NaN for invalid arguments. */
+double oracle_fap(double Pn, int64_t Nt, int64_t Nf)
+{
+    if (Nt < 4 || Nf < 1 || !(Pn >= 0.0) || Pn > 0.5 * (double)Nt)
+        return NAN;
+    double z = 2.0 * Pn / (double)Nt;                     /* in [0, 1] */
+    double log_tail = 0.5 * (double)(Nt - 3) * log1p(-z); /* log of (1-z)^((Nt-3)/2) */
+    double tail = exp(log_tail);                          /* single-frequency FAP */
+    if (tail >= 1.0)
+        return 1.0;
+    return -expm1((double)Nf * log1p(-tail));
+}
+
+/* Spectral window W(f_k) = (sum_j cos 2 pi f_k t_j)^2 + (sum_j sin 2 pi f_k t_j)^2:
+   the squared modulus of the transform of the sampling pattern alone. */
+int oracle_window(const double *t, int64_t Nt, double f_min, double df,
+                  int64_t Nf, double *W, int nthreads)
+{
+    if (!t || !W || Nt < 1 || Nf < 0 || !isfinite(f_min) || !isfinite(df))
+        return ORACLE_ERR_ARG;
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t k = 0; k < Nf; ++k) {
+        double f = f_min + (double)k * df;
+        nsum C = {0, 0}, S = {0, 0};
+        for (int64_t j = 0; j < Nt; ++j) {
+            double p = f * t[j];
+            double phi = p - nearbyint(p);
+            nsum_add(&C, cos(TWO_PI * phi));
+            nsum_add(&S, sin(TWO_PI * phi));
+        }
+        double c = nsum_get(&C), s = nsum_get(&S);
+        W[k] = c * c + s * s;
+    }
+    return ORACLE_OK;
+}
+
+int oracle_max_threads(void) { return omp_get_max_threads(); }
