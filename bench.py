@@ -1,0 +1,213 @@
+"""Throughput benchmark of the direct Lomb-Scargle periodogram on one MI355X.
+
+One step = one full call of the hot path (normalization prep, the
+periodogram kernel, split-axis reduction and FP64 epilogue) on one
+synthetic light curve already resident in HBM.  Prints one JSON line.
+
+Default workload: one long light curve, Nt = 65,536 samples at 2-min cadence
+with gaps and jitter, 5 sinusoids + noise, Nf = 131,072 frequencies
+(oversampling 4).  The split-precision path is the headline value; the plain
+(naive FP32 phase) path is timed beside it.  The CPU baseline is the FP64
+oracle on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Nt·Nf terms/s (split-FP32 vs plain) at max|ΔPn|≤1e-4; % FP32 VALU peak"
+FLOP_PER_TERM = 13          # phase mul/round/sub 3, sin+cos 2, four FMAs 8
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz, packed issue)
+REL_TOL = 1e-4
+
+WORKLOADS = {
+    "c1": ("single long light curve: Nt=65536 at 2-min cadence with 20% gaps and 10-s jitter, "
+           "5 sinusoids (1-20 c/d, amplitudes 1e-3..1e-1) + 1e-3 noise, Nf=131072, oversampling 4"),
+    "c0": "plain single light curve: Nt=1000 uniform in [0,100] d, 0.37 c/d sinusoid + noise, Nf=2000",
+    "c2": ("precision stress: Nt=100000 over 3650 d after epoch 2455000 d, 13.7 c/d sinusoid + N(0,1), "
+           "Nf=1048576 up to 50 c/d"),
+    "paper": "paper-shaped stand-in: Nt=382003 on a 32-s grid over 150 d, Nf=1528064",
+}
+
+
+def make_curve(name):
+    from paper_1007_1658_amd import synth
+    return {"c0": synth.c0, "c1": synth.c1, "c2": synth.c2, "paper": synth.paper_standin}[name]()
+
+
+def kernel_source_hash():
+    p = os.path.join(ROOT, "paper_1007_1658_amd", "csrc", "pgram_kernels.hip")
+    with open(p, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_name, workload):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
+    were taken on the current kernel source; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    try:
+        with open(p) as f:
+            d = json.load(f)
+        e = d.get(f"{kernel_name}|{workload}")
+        if not e or e.get("source_sha") != kernel_source_hash():
+            return None
+        return float(e["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def sampled_error(curve, Pg, n=256, seed=0):
+    import oracle
+    g = np.random.default_rng(seed)
+    kpk = int(np.argmax(Pg))
+    k = np.unique(np.concatenate([g.integers(0, curve.Nf, n),
+                                  np.arange(max(0, kpk - 4), min(curve.Nf, kpk + 5))]))
+    P = oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
+    return float(np.max(np.abs(Pg[k].astype(np.float64) - P)) / P.max())
+
+
+def cpu_baseline(curve, target_s):
+    """The oracle as it stands, on all host cores, over a frequency subset."""
+    import oracle
+    cores = oracle.max_threads()
+    g = np.random.default_rng(7)
+    k = np.sort(g.choice(curve.Nf, size=min(curve.Nf, 64), replace=False))
+    t0 = time.perf_counter()
+    oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
+    cal = max(time.perf_counter() - t0, 1e-3)
+    nb = int(min(curve.Nf, max(64, 64 * target_s / cal)))
+    k = np.sort(g.choice(curve.Nf, size=nb, replace=False))
+    t0 = time.perf_counter()
+    oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
+    el = time.perf_counter() - t0
+    return {
+        "value": curve.Nt * nb / el,
+        "unit": "terms/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"FP64 two-pass oracle over all Nt={curve.Nt} samples at {nb} of the {curve.Nf} "
+                   f"frequencies (random subset), {el:.1f} s on {cores} threads"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--no-tune", action="store_true", help="use the heuristic launch shape")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the periodogram would shard by frequency; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1007_1658_amd as lsp
+
+    assert torch.cuda.is_available(), "no GPU"
+    curve = make_curve(args.config)
+    t = torch.from_numpy(curve.t).cuda()
+    x = torch.from_numpy(curve.x).cuda()
+    Pn = torch.empty(curve.Nf, dtype=torch.float32, device="cuda")
+
+    tile = None
+    if not args.no_tune:
+        tile, _ = lsp.lsp_autotune(curve.Nt, curve.Nf, "split")
+        lsp.lsp_autotune(curve.Nt, curve.Nf, "naive")
+
+    def run_split():
+        lsp.lsp_periodogram(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pn)
+
+    # accuracy of the exact configuration that is timed
+    run_split()
+    torch.cuda.synchronize()
+    err_split = sampled_error(curve, Pn.cpu().numpy())
+
+    lsp.lsp_profile_enable(True)
+    sec = time_steps(run_split, args.steps, args.warmup)
+    k_ms, k_n, k_name = lsp.lsp_profile_read()
+    lsp.lsp_profile_enable(False)
+    # warm-up launches are included in the profile record; average over all of them
+    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    terms = curve.Nt * curve.Nf
+    value = terms / sec
+
+    plain = None
+    if not args.no_plain:
+        Pp = torch.empty_like(Pn)
+
+        def run_plain():
+            lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pp, phase="naive")
+
+        run_plain()
+        torch.cuda.synchronize()
+        err_plain = sampled_error(curve, Pp.cpu().numpy())
+        sec_p = time_steps(run_plain, max(5, args.steps // 2), 2)
+        plain = {"value": terms / sec_p, "ms_per_step": sec_p * 1e3, "max_rel_err": err_plain,
+                 "meets_1e-4": bool(err_plain <= REL_TOL)}
+
+    achieved = FLOP_PER_TERM * terms / k_avg_s / 1e12
+    traffic = traffic_from_profiles(k_name, args.config)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "terms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "name": args.config, "Nt": curve.Nt, "Nf": curve.Nf,
+                   "phase": "split", "tile": tile},
+        "max_rel_err": err_split,
+        "meets_1e-4": bool(err_split <= REL_TOL),
+        "plain": plain,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_TFLOPS,
+            "traffic": traffic,
+            "kernel": k_name,
+            "kernel_avg_ms": k_avg_s * 1e3,
+            "flop_per_term": FLOP_PER_TERM,
+        },
+        "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

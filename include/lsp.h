@@ -1,0 +1,204 @@
+/*
+ * lsp.h -- C ABI of libmi355lsp, a gfx950 (MI355X) implementation of the
+ * direct O(Nt * Nf) normalized Lomb-Scargle periodogram of Townsend,
+ * "Fast Calculation of the Lomb-Scargle Periodogram Using Graphics
+ * Processing Units".
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named "device" are HIP device memory owned by the caller; the
+ *    library never frees or retains them after the call returns (graphs it
+ *    caches hold them until the next call with another shape, see
+ *    lsp_periodogram_batched).  Pointers named "host" are ordinary host
+ *    memory, read during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every GPU entry point is asynchronous on that stream unless stated.
+ *  - Argument validation is synchronous, happens on the host before any HIP
+ *    call, and reports LSP_ERR_INVALID_ARG.  HIP failures report LSP_ERR_HIP;
+ *    lsp_last_error() gives the HIP message.
+ *  - The frequency grid is f_k = f_min + k * df, k = 0 .. Nf-1, formed from k
+ *    in FP64.  The paper's grid (Eq. (9), Section 4.3) is f_min = df;
+ *    lsp_grid_paper() builds it from the oversampling and high factors of
+ *    Eqs. (10)-(11).
+ *  - The series is normalized inside the library (Section 3, opening
+ *    paragraph): mean removed, scaled to unit population variance.  So Pn is
+ *    invariant to x -> a x + b and 0 <= Pn <= Nt/2.
+ *  - Thread safety: calls may come from several host threads; each device
+ *    and stream gets its own workspace, guarded by a mutex.
+ */
+#ifndef MI355LSP_LSP_H
+#define MI355LSP_LSP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lsp_status {
+    LSP_OK = 0,
+    LSP_ERR_INVALID_ARG = -1,   /* rejected on the host before any GPU work */
+    LSP_ERR_ZERO_VARIANCE = -2, /* x is constant (reported only when checked) */
+    LSP_ERR_NO_DEVICE = -3,     /* no HIP device, or not a gfx950 device */
+    LSP_ERR_HIP = -4,           /* a HIP runtime call failed */
+    LSP_ERR_MODEL = -5,         /* surrogate model missing, corrupt or mismatched */
+    LSP_ERR_CAPTURE = -6,       /* the call would allocate while the stream is captured */
+    LSP_ERR_UNSUPPORTED = -7    /* option combination not built into the library */
+} lsp_status;
+
+/* How the phase f_k * t_j is reduced to revolutions in [-1/2, 1/2] (Section
+   4.4 describes the paper's FP32 reduction by the nearest integer). */
+typedef enum lsp_phase_mode {
+    /* Default.  Times are shifted by t_ref = (t_min + t_max)/2 (Pn does not
+       depend on a time shift) and held as t' = t_hi + t_lo (two FP32); the
+       product f * t' is formed and reduced in FP64; the reduced phase and all
+       trigonometry and sums are FP32. */
+    LSP_PHASE_SPLIT = 0,
+    /* The paper's arithmetic: raw t rounded to FP32 (epoch included), f in
+       FP32, ft - rint(ft) in FP32.  Kept as the comparison baseline; it loses
+       accuracy on long or epoch-offset baselines. */
+    LSP_PHASE_NAIVE = 1,
+    /* Like SPLIT, but the product is an all-FP32 error-free product of
+       (f_hi + f_lo)(t_hi + t_lo) (FMA-based two-product), no FP64. */
+    LSP_PHASE_SPLIT32 = 2
+} lsp_phase_mode;
+
+/* How (cos, sin) of each term are produced. */
+typedef enum lsp_trig_mode {
+    LSP_TRIG_AUTO = 0,   /* autotuned / heuristic choice */
+    /* Every term evaluates its own phase and hardware sin/cos. */
+    LSP_TRIG_DIRECT = 1,
+    /* Each lane owns m frequencies spaced 64 df apart.  The first is
+       evaluated directly per sample, the second by one rotation through the
+       per-sample step angle 2 pi 64 df t'_j (computed in FP64 once per
+       sample), the rest by the three-term recurrence
+       c_{m+1} = 2 cos(step) c_m - c_{m-1} (and likewise for sin).  Re-seeded
+       exactly at every sample.  Only with LSP_PHASE_SPLIT / SPLIT32. */
+    LSP_TRIG_RECUR = 2
+} lsp_trig_mode;
+
+/* Launch shape of the periodogram kernel.  All-zero = library's choice. */
+typedef struct lsp_tile {
+    int32_t trig;   /* lsp_trig_mode */
+    int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4,8,12,16 */
+    int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2, 4 or 8 */
+    int32_t splits; /* workgroups sharing one frequency block along the sample
+                       axis (1 = none); partials merged in fixed order in FP64 */
+} lsp_tile;
+
+typedef struct lsp_options {
+    int32_t phase;  /* lsp_phase_mode */
+    int32_t check;  /* non-zero: synchronize the stream at the end of the call
+                       and return LSP_ERR_ZERO_VARIANCE for a constant x */
+    lsp_tile tile;  /* all-zero fields = autotuned / heuristic choice */
+} lsp_options;
+
+/* ---- single light curve ------------------------------------------------------
+
+   Normalized periodogram of Eq. (1) with tau of Eq. (2), computed in the
+   single-pass form of Eqs. (5)-(8) (Section 3): per frequency the sums
+   XC, XS, CC, CS over all samples, SS = Nt - CC, then tau from
+   tan 2wtau = 2 CS / (CC - SS) (atan2 branch, atan2(0,0) = 0) and Pn by
+   Eq. (5).  A term of Eq. (5) whose denominator is <= 1e-12 Nt is 0.
+
+   t   device FP64 [Nt]  sampling times, any order, finite.
+   x   device FP32 [Nt]  values, finite.
+   Nt  >= 2.
+   f_min finite, >= 0;  df finite, > 0;  Nf >= 1.
+   Pn  device FP32 [Nf]  output, fully written: Pn[k] = Pn(f_min + k df).
+   Errors: LSP_ERR_INVALID_ARG for null pointers or out-of-range sizes;
+   a constant x yields Pn = 0 everywhere (LSP_ERR_ZERO_VARIANCE only with
+   lsp_options.check). */
+lsp_status lsp_periodogram(const double *t, const float *x, int64_t Nt,
+                           double f_min, double df, int64_t Nf, float *Pn,
+                           void *stream);
+
+/* As lsp_periodogram, with explicit phase mode and launch shape.
+   opt may be NULL (defaults).  LSP_ERR_UNSUPPORTED for a tile the library
+   was not built with (see lsp_tile) or RECUR with NAIVE phase. */
+lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt,
+                              double f_min, double df, int64_t Nf, float *Pn,
+                              void *stream, const lsp_options *opt);
+
+/* ---- many light curves in one persistent launch ------------------------------
+
+   Curve c owns samples [off[c], off[c+1]) of t and x and its own grid
+   f_min[c] + k df[c], k < Nf[c].  All curves are processed by one
+   persistent kernel that takes (curve, frequency block) work items from a
+   device queue, longest curves first; the whole sequence (queue reset,
+   per-curve normalization, periodogram, per-curve reduction) is captured
+   once into a hipGraph per batch shape and replayed on later calls with the
+   same shape and pointers.
+
+   t, x      device FP64 / FP32 [off[n]]
+   off       host int64 [n+1], off[0] = 0, non-decreasing, each Nt >= 2
+   f_min, df host FP64 [n];  Nf host int64 [n] (>= 1)
+   Pn        device FP32 [sum Nf] or NULL; curve c at offset sum_{i<c} Nf[i]
+   pmax      device FP32 [n]   max_k Pn of curve c (NaN if its x is constant)
+   kbest     device int64 [n] or NULL: argmax k, lowest k on exact ties
+   fbest     device FP64 [n] or NULL: f_min[c] + kbest df[c]
+   t_ns      device uint64 [2n] or NULL: device timestamps (ns, relative to
+             the start of the launch) at which curve c's first work item
+             started and its last work item finished.
+   Errors: LSP_ERR_INVALID_ARG; LSP_ERR_CAPTURE when the stream is being
+   captured by the caller and this shape has not been prepared by an
+   earlier uncaptured call. */
+lsp_status lsp_periodogram_batched(const double *t, const float *x,
+                                   const int64_t *off, int32_t n_curves,
+                                   const double *f_min, const double *df,
+                                   const int64_t *Nf, float *Pn, float *pmax,
+                                   int64_t *kbest, double *fbest,
+                                   uint64_t *t_ns, void *stream);
+
+/* ---- autotuner -----------------------------------------------------------------
+
+   Times the built launch shapes of the single-curve kernel on synthetic data
+   of size (Nt, Nf) on `stream` (synchronous), keeps the fastest in the
+   in-memory cache (keyed by device arch, CU count, phase mode and the
+   power-of-two buckets of Nt and Nf) and returns it.  Later calls in the
+   same buckets with an all-zero tile use it.  best_ms may be NULL. */
+lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream,
+                        lsp_tile *best, double *best_ms);
+/* JSON persistence of the tuner cache; path NULL = $LSP_TUNE_CACHE. */
+lsp_status lsp_tune_cache_save(const char *path);
+lsp_status lsp_tune_cache_load(const char *path);
+
+/* ---- profiling hook ------------------------------------------------------------
+
+   While enabled, every launch of the main periodogram kernel is bracketed
+   by HIP events recorded on the stream it runs on.  lsp_profile_read
+   synchronizes those events and returns the total kernel time (ms), the
+   number of launches and the kernel's symbol name (truncated to name_len).
+   Enabling clears previous records. */
+lsp_status lsp_profile_enable(int32_t on);
+lsp_status lsp_profile_read(double *total_ms, int64_t *launches, char *name,
+                            int32_t name_len);
+
+/* ---- host-only helpers (no GPU needed) -------------------------------------------
+
+   Grid of Eqs. (9)-(11): df = 1/(F_over (t_max - t_min)), f_min = df,
+   Nf = ceil(F_high F_over Nt / 2), then rounded up to a multiple of round_to
+   (>= 1; the paper's kernel needs a multiple of its 256-thread block).
+   Errors: LSP_ERR_INVALID_ARG for t_max <= t_min, Nt < 2, F_over <= 0,
+   F_high <= 0, round_to < 1 or a null output pointer. */
+lsp_status lsp_grid_paper(double t_min, double t_max, int64_t Nt,
+                          double F_over, double F_high, int32_t round_to,
+                          double *f_min, double *df, int64_t *Nf);
+
+/* Eq. (3): Q = 1 - [1 - (1 - 2 Pn/Nt)^((Nt-3)/2)]^Nf, evaluated with
+   log1p/expm1.  NaN when Nt < 4, Nf < 1 or Pn outside [0, Nt/2]. */
+double lsp_fap_analytic(double Pn, int64_t Nt, int64_t Nf);
+
+const char *lsp_status_string(lsp_status s);
+/* Last HIP error message seen by this host thread ("" if none). */
+const char *lsp_last_error(void);
+/* Library version string. */
+const char *lsp_version(void);
+/* Number of visible gfx950 devices (0 when there is none; never fails). */
+int32_t lsp_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MI355LSP_LSP_H */

@@ -1,1 +1,268 @@
-"""MI355X-native direct Lomb-Scargle periodogram (placeholder binding)."""
+"""mi355lsp -- MI355X (gfx950) direct normalized Lomb-Scargle periodogram.
+
+Thin ctypes binding over the C ABI of libmi355lsp.so (include/lsp.h); the
+Python functions carry the C names and only marshal arguments: every step
+of the computation runs in the library's HIP kernels.  Torch tensors supply
+device memory and streams.  There is no CPU fallback: if the library is not
+built, or no gfx950 device is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmi355lsp.so")
+
+LSP_OK = 0
+LSP_ERR_INVALID_ARG = -1
+LSP_ERR_ZERO_VARIANCE = -2
+LSP_ERR_NO_DEVICE = -3
+LSP_ERR_HIP = -4
+LSP_ERR_MODEL = -5
+LSP_ERR_CAPTURE = -6
+LSP_ERR_UNSUPPORTED = -7
+
+LSP_PHASE_SPLIT = 0
+LSP_PHASE_NAIVE = 1
+LSP_PHASE_SPLIT32 = 2
+
+LSP_TRIG_AUTO = 0
+LSP_TRIG_DIRECT = 1
+LSP_TRIG_RECUR = 2
+
+PHASES = {"split": LSP_PHASE_SPLIT, "naive": LSP_PHASE_NAIVE, "split32": LSP_PHASE_SPLIT32}
+TRIGS = {"auto": LSP_TRIG_AUTO, "direct": LSP_TRIG_DIRECT, "recur": LSP_TRIG_RECUR}
+
+
+class LspError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {lsp_status_string(status)} ({status})"
+        if detail:
+            msg += f": {detail}"
+        super().__init__(msg)
+
+
+class lsp_tile(ctypes.Structure):
+    _fields_ = [("trig", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("waves", ctypes.c_int32), ("splits", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {"trig": self.trig, "m": self.m, "waves": self.waves, "splits": self.splits}
+
+
+class lsp_options(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("check", ctypes.c_int32), ("tile", lsp_tile)]
+
+
+_lib = None
+
+# symbol -> (restype, argtypes); the exported surface of include/lsp.h
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_D = ctypes.c_double
+SIGNATURES = {
+    "lsp_periodogram": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P]),
+    "lsp_periodogram_ex": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P, ctypes.POINTER(lsp_options)]),
+    "lsp_periodogram_batched": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lsp_autotune": (_I32, [_I64, _I64, _I32, _P, ctypes.POINTER(lsp_tile), ctypes.POINTER(_D)]),
+    "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
+    "lsp_tune_cache_load": (_I32, [ctypes.c_char_p]),
+    "lsp_profile_enable": (_I32, [_I32]),
+    "lsp_profile_read": (_I32, [ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.c_char_p, _I32]),
+    "lsp_grid_paper": (_I32, [_D, _D, _I64, _D, _D, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
+                              ctypes.POINTER(_I64)]),
+    "lsp_fap_analytic": (_D, [_D, _I64, _I64]),
+    "lsp_status_string": (ctypes.c_char_p, [_I32]),
+    "lsp_last_error": (ctypes.c_char_p, []),
+    "lsp_version": (ctypes.c_char_p, []),
+    "lsp_device_count": (_I32, []),
+}
+
+
+def lib():
+    """The loaded libmi355lsp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "(or python paper_1007_1658_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def lsp_status_string(status: int) -> str:
+    return lib().lsp_status_string(int(status)).decode()
+
+
+def lsp_last_error() -> str:
+    return lib().lsp_last_error().decode()
+
+
+def lsp_version() -> str:
+    return lib().lsp_version().decode()
+
+
+def lsp_device_count() -> int:
+    return int(lib().lsp_device_count())
+
+
+def _check(status: int, where: str):
+    if status != LSP_OK:
+        raise LspError(status, where, lsp_last_error())
+
+
+# ---- host-only helpers --------------------------------------------------------------
+
+def lsp_grid_paper(t_min: float, t_max: float, Nt: int, F_over: float = 4.0, F_high: float = 1.0,
+                   round_to: int = 1):
+    """(f_min, df, Nf) of the paper's grid, Eqs. (9)-(11)."""
+    f_min, df, nf = _D(), _D(), _I64()
+    _check(lib().lsp_grid_paper(float(t_min), float(t_max), int(Nt), float(F_over), float(F_high),
+                                int(round_to), ctypes.byref(f_min), ctypes.byref(df), ctypes.byref(nf)),
+           "lsp_grid_paper")
+    return f_min.value, df.value, int(nf.value)
+
+
+def lsp_fap_analytic(Pn: float, Nt: int, Nf: int) -> float:
+    """Eq. (3) false-alarm probability."""
+    return float(lib().lsp_fap_analytic(float(Pn), int(Nt), int(Nf)))
+
+
+# ---- device entry points --------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_tensor(a, dtype, name):
+    torch = _torch()
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if a.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {a.dtype}")
+    if not a.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return a
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.data_ptr()) if a is not None else None
+
+
+def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None):
+    """Pn[k] = Pn(f_min + k df), k < Nf, for device t (float64) and x (float32)."""
+    return lsp_periodogram_ex(t, x, f_min, df, Nf, Pn=Pn, stream=stream)
+
+
+def lsp_periodogram_ex(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None,
+                       phase="split", trig="auto", m=0, waves=0, splits=0, check=False):
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(x, torch.float32, "x")
+    if t.ndim != 1 or x.shape != t.shape:
+        raise ValueError("t and x must be 1-D and of equal length")
+    if Pn is None:
+        Pn = torch.empty(int(Nf), dtype=torch.float32, device=t.device)
+    _dev_tensor(Pn, torch.float32, "Pn")
+    if Pn.numel() < int(Nf):
+        raise ValueError("Pn is shorter than Nf")
+    opt = lsp_options()
+    opt.phase = PHASES[phase] if isinstance(phase, str) else int(phase)
+    opt.check = 1 if check else 0
+    opt.tile.trig = TRIGS[trig] if isinstance(trig, str) else int(trig)
+    opt.tile.m, opt.tile.waves, opt.tile.splits = int(m), int(waves), int(splits)
+    with torch.cuda.device(t.device):
+        st = lib().lsp_periodogram_ex(_ptr(t), _ptr(x), t.numel(), float(f_min), float(df), int(Nf),
+                                      _ptr(Pn), _stream_ptr(stream), ctypes.byref(opt))
+    _check(st, "lsp_periodogram_ex")
+    return Pn
+
+
+def lsp_periodogram_batched(t, x, off, f_min, df, Nf, want_pn=False, want_times=False, stream=None,
+                            out=None):
+    """Per-curve (pmax, kbest, fbest[, Pn CSR][, t_ns]) of a CSR batch in one persistent launch.
+
+    t, x: device tensors (float64 / float32) holding all curves back to back.
+    off, f_min, df, Nf: host arrays (numpy) describing the batch shape.
+    out: optional dict of preallocated device outputs (reused across calls so
+    that the cached hipGraph is replayed).
+    """
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(x, torch.float32, "x")
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    f_min = np.ascontiguousarray(np.asarray(f_min, dtype=np.float64))
+    df = np.ascontiguousarray(np.asarray(df, dtype=np.float64))
+    Nf = np.ascontiguousarray(np.asarray(Nf, dtype=np.int64))
+    n = off.size - 1
+    if n < 1 or f_min.size != n or df.size != n or Nf.size != n:
+        raise ValueError("batch arrays disagree in length")
+    if int(off[-1]) != t.numel() or x.numel() != t.numel():
+        raise ValueError("off[-1] must equal the number of samples")
+    dev = t.device
+    if out is None:
+        out = {}
+    if "pmax" not in out:
+        out["pmax"] = torch.empty(n, dtype=torch.float32, device=dev)
+        out["kbest"] = torch.empty(n, dtype=torch.int64, device=dev)
+        out["fbest"] = torch.empty(n, dtype=torch.float64, device=dev)
+    if want_pn and "Pn" not in out:
+        out["Pn"] = torch.empty(int(Nf.sum()), dtype=torch.float32, device=dev)
+    if want_times and "t_ns" not in out:
+        out["t_ns"] = torch.empty(2 * n, dtype=torch.int64, device=dev)
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    with torch.cuda.device(dev):
+        st = lib().lsp_periodogram_batched(
+            _ptr(t), _ptr(x), hp(off), n, hp(f_min), hp(df), hp(Nf),
+            _ptr(out.get("Pn")), _ptr(out["pmax"]), _ptr(out["kbest"]), _ptr(out["fbest"]),
+            _ptr(out.get("t_ns")), _stream_ptr(stream))
+    _check(st, "lsp_periodogram_batched")
+    return out
+
+
+def lsp_autotune(Nt: int, Nf: int, phase="split", stream=None):
+    """(tile dict, best ms) for (Nt, Nf); also stored in the library's tuner cache."""
+    tile = lsp_tile()
+    ms = _D()
+    ph = PHASES[phase] if isinstance(phase, str) else int(phase)
+    _check(lib().lsp_autotune(int(Nt), int(Nf), ph, _stream_ptr(stream), ctypes.byref(tile),
+                              ctypes.byref(ms)), "lsp_autotune")
+    return tile.as_dict(), ms.value
+
+
+def lsp_tune_cache_save(path=None):
+    _check(lib().lsp_tune_cache_save(path.encode() if path else None), "lsp_tune_cache_save")
+
+
+def lsp_tune_cache_load(path=None):
+    _check(lib().lsp_tune_cache_load(path.encode() if path else None), "lsp_tune_cache_load")
+
+
+def lsp_profile_enable(on: bool = True):
+    _check(lib().lsp_profile_enable(1 if on else 0), "lsp_profile_enable")
+
+
+def lsp_profile_read():
+    """(total ms, launches, kernel name) of the main kernel since lsp_profile_enable."""
+    tot, n = _D(), _I64()
+    buf = ctypes.create_string_buffer(256)
+    _check(lib().lsp_profile_read(ctypes.byref(tot), ctypes.byref(n), buf, 256), "lsp_profile_read")
+    return tot.value, int(n.value), buf.value.decode()

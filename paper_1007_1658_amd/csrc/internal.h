@@ -1,0 +1,104 @@
+// internal.h -- declarations shared by the library's host code and kernels.
+// Not part of the public ABI (that is include/lsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lsp.h"
+
+namespace lsp {
+
+constexpr int kWave = 64;          // gfx950 wavefront width
+constexpr int kMaxWaves = 8;       // waves per workgroup supported by the kernels
+constexpr int kTile = 64;          // samples staged per wave per tile (one per lane)
+constexpr int kFoldTiles = 4;      // tiles between compensated folds of the FP32 partials
+
+// Per-curve scalars written by the prep kernels and read by the rest.
+struct CurveStats {
+    double mean;     // sample mean of x
+    double var;      // population variance of x
+    double inv_var;  // 1/var, 0 when var == 0
+    double t_ref;    // time origin removed from t (0 in NAIVE mode)
+    double t_min, t_max;
+    int32_t zero_var;
+    int32_t pad_;
+};
+
+// Partial moments of a slice of the series (count, mean, M2, time range),
+// merged with Chan et al.'s pairwise update.
+struct Moments {
+    double n, mean, m2, tmin, tmax;
+};
+
+// Per-sample records (SoA, FP32) staged by the periodogram kernels.
+struct Records {
+    float *th;  // t' hi  (t' = t - t_ref; NAIVE: fl32(t))
+    float *tl;  // t' lo  (t' - th, rounded; NAIVE: 0)
+    float *xv;  // x - mean
+    float *rc;  // cos(2 pi * 64 df * t')  (step of the frequency recurrence)
+    float *rs;  // sin(2 pi * 64 df * t')
+};
+
+struct PgramArgs {
+    Records rec;
+    const CurveStats *stats;
+    int64_t Nt;
+    int64_t chunk;      // samples per split (multiple of kTile)
+    double f_min, df;
+    int64_t Nf;
+    float *Pn;          // written when splits == 1
+    double *part;       // [splits][4][Nf] FP64 partial sums when splits > 1
+    int32_t splits;
+};
+
+// Batched work item: one wave computes 64*m frequencies of one curve.
+struct BatchItem {
+    int32_t curve;
+    int32_t fblock;
+};
+
+struct BatchCurve {
+    int64_t off;        // first sample
+    int64_t Nt;
+    int64_t Nf;
+    int64_t pn_off;     // first output frequency in the CSR Pn array
+    double f_min, df;
+};
+
+struct BatchArgs {
+    Records rec;              // CSR, same offsets as the input samples
+    CurveStats *stats;        // [n]
+    const BatchCurve *curves; // [n]
+    const BatchItem *items;   // [n_items], longest curves first
+    int32_t n_items;
+    int32_t n_curves;
+    uint32_t *queue;          // [1] next item
+    unsigned long long *key;  // [n] (float bits of max Pn) << 32 | ~k
+    unsigned long long *tbeg; // [n]
+    unsigned long long *tend; // [n]
+    unsigned long long *t0;   // [1] launch start
+    float *Pn;                // nullable
+    float *pmax;
+    int64_t *kbest;           // nullable
+    double *fbest;            // nullable
+    uint64_t *t_ns;           // nullable
+    const double *t;          // raw inputs (prep)
+    const float *x;
+};
+
+// ---- kernel launchers (pgram_kernels.hip) --------------------------------------
+hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_df,
+                       int phase, Moments *moments, int n_moment_blocks,
+                       CurveStats *stats, Records rec, hipStream_t s);
+hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hipStream_t s,
+                        hipEvent_t ev0, hipEvent_t ev1);
+const char *pgram_kernel_name(int phase, const lsp_tile &tile);
+bool pgram_tile_supported(int phase, const lsp_tile &tile);
+
+hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,
+                          hipStream_t s);
+int batched_m();
+hipError_t batched_occupancy(int waves, int *blocks_per_cu);
+
+}  // namespace lsp

@@ -1,0 +1,681 @@
+// lsp_host.cpp -- host side of the C ABI declared in include/lsp.h:
+// validation, device checks, per-(device, stream) workspaces, launch-shape
+// choice, hipGraph capture of batched calls, profiling hook, host helpers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "internal.h"
+#include "tuner.h"
+
+namespace lsp {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int64_t kMaxNt = (int64_t)1 << 31;   // sample count limit (32-bit tile indices)
+constexpr int64_t kMaxNf = ((int64_t)1 << 32) - 1;  // batched argmax key holds k in 32 bits
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+lsp_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return LSP_ERR_HIP;
+}
+
+struct DeviceInfo {
+    bool ok = false;
+    int cus = 0;
+    std::string arch;
+};
+
+struct Buffer {
+    void *ptr = nullptr;
+    size_t size = 0;
+};
+
+struct BatchGraph {
+    uint64_t key = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct StreamCtx {
+    Buffer ws;        // single-curve workspace
+    Buffer bws;       // batched workspace
+    uint64_t plan_key = 0;  // batch plan currently resident in bws
+    BatchGraph graph;
+};
+
+struct Context {
+    std::mutex mu;
+    std::map<int, DeviceInfo> dev;
+    std::map<std::pair<int, hipStream_t>, std::unique_ptr<StreamCtx>> streams;
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    std::string prof_name;
+};
+
+Context &ctx()
+{
+    static Context *c = new Context();  // never destroyed: safe at process exit
+    return *c;
+}
+
+// requires ctx().mu held
+lsp_status device_info(int *dev_out, DeviceInfo **info)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        g_last_error = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return LSP_ERR_NO_DEVICE;
+    }
+    auto it = ctx().dev.find(dev);
+    if (it == ctx().dev.end()) {
+        DeviceInfo di;
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e == hipSuccess) {
+            di.arch = prop.gcnArchName;
+            di.cus = prop.multiProcessorCount;
+            di.ok = di.arch.rfind("gfx950", 0) == 0;
+        }
+        it = ctx().dev.emplace(dev, di).first;
+    }
+    if (!it->second.ok) {
+        g_last_error = "device " + std::to_string(dev) + " is not gfx950 (" + it->second.arch + ")";
+        return LSP_ERR_NO_DEVICE;
+    }
+    *dev_out = dev;
+    *info = &it->second;
+    return LSP_OK;
+}
+
+StreamCtx &stream_ctx(int dev, hipStream_t s)
+{
+    auto &p = ctx().streams[{dev, s}];
+    if (!p) p.reset(new StreamCtx());
+    return *p;
+}
+
+bool stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return false;
+    return st == hipStreamCaptureStatusActive;
+}
+
+// grow-only buffer; never grows while the stream is captured
+lsp_status ensure(Buffer &b, size_t need, hipStream_t s)
+{
+    if (b.size >= need) return LSP_OK;
+    if (stream_capturing(s)) {
+        g_last_error = "workspace would grow during stream capture";
+        return LSP_ERR_CAPTURE;
+    }
+    hipError_t e;
+    if (b.ptr) {
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipFree(b.ptr);
+        if (e != hipSuccess) return hip_fail(e, "hipFree");
+        b.ptr = nullptr;
+        b.size = 0;
+    }
+    size_t sz = std::max(need, (size_t)1 << 20);
+    e = hipMalloc(&b.ptr, sz);
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc(workspace)");
+    b.size = sz;
+    return LSP_OK;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---- single-curve workspace layout ----------------------------------------------
+struct Layout {
+    size_t stats, moments, th, tl, xv, rc, rs, part, total;
+};
+
+Layout layout(int64_t Nt, int64_t Nf, int splits, int n_mom)
+{
+    Layout L;
+    size_t o = 0;
+    L.stats = o;
+    o = align_up(o + sizeof(CurveStats));
+    L.moments = o;
+    o = align_up(o + sizeof(Moments) * (size_t)n_mom);
+    const size_t fb = align_up(sizeof(float) * (size_t)Nt);
+    L.th = o;
+    o += fb;
+    L.tl = o;
+    o += fb;
+    L.xv = o;
+    o += fb;
+    L.rc = o;
+    o += fb;
+    L.rs = o;
+    o += fb;
+    L.part = o;
+    if (splits > 1) o = align_up(o + sizeof(double) * 4 * (size_t)Nf * (size_t)splits);
+    L.total = o;
+    return L;
+}
+
+int moment_blocks(int64_t Nt) { return (int)std::min<int64_t>(256, std::max<int64_t>(1, (Nt + 1023) / 1024)); }
+
+}  // namespace
+
+// ---- launch-shape choice -------------------------------------------------------------
+
+int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus)
+{
+    const int64_t per_wave = (int64_t)kWave * m;
+    const int64_t nfb = (Nf + per_wave - 1) / per_wave;
+    const int64_t target = (int64_t)cus * 16;  // about four waves per SIMD
+    int64_t s = (target + nfb - 1) / nfb;
+    const int64_t by_len = std::max<int64_t>(1, Nt / 256);  // at least 256 samples per split
+    s = std::min<int64_t>(s, by_len);
+    s = std::min<int64_t>(s, 64);
+    // keep the FP64 partials under 1 GiB
+    while (s > 1 && (double)s * 32.0 * (double)Nf > (double)(1u << 30)) --s;
+    return (int)std::max<int64_t>(1, s);
+}
+
+lsp_tile default_tile(int phase, int64_t Nt, int64_t Nf, int cus)
+{
+    lsp_tile t;
+    if (phase == LSP_PHASE_NAIVE) {
+        t.trig = LSP_TRIG_DIRECT;
+        t.m = 1;
+    } else {
+        t.trig = LSP_TRIG_RECUR;
+        t.m = 8;
+    }
+    t.waves = 4;
+    t.splits = heuristic_splits(Nt, Nf, t.m, cus);
+    return t;
+}
+
+// chunk (multiple of the tile) and effective number of splits
+static void split_geometry(int64_t Nt, int splits, int64_t *chunk, int *eff)
+{
+    int64_t c = (Nt + splits - 1) / splits;
+    c = (c + kTile - 1) / kTile * kTile;
+    *chunk = c;
+    *eff = (int)((Nt + c - 1) / c);
+}
+
+// Runs prep + main (+ reduce) for one curve on `s`.  Caller holds no lock.
+static lsp_status run_single(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                             int64_t Nf, float *Pn, hipStream_t s, int phase, lsp_tile tile,
+                             const CurveStats **stats_out, bool allow_profile)
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    lsp_status st = device_info(&dev, &di);
+    if (st != LSP_OK) return st;
+    if (tile.trig == 0 || tile.m == 0 || tile.waves == 0) {
+        lsp_tile tuned;
+        if (tuner_lookup(di->arch, di->cus, phase, Nt, Nf, &tuned)) {
+            if (tile.trig == 0) tile.trig = tuned.trig;
+            if (tile.m == 0) tile.m = tuned.m;
+            if (tile.waves == 0) tile.waves = tuned.waves;
+            if (tile.splits == 0) tile.splits = tuned.splits;
+        }
+        lsp_tile d = default_tile(phase, Nt, Nf, di->cus);
+        if (tile.trig == 0) tile.trig = d.trig;
+        if (tile.m == 0) tile.m = (tile.trig == d.trig) ? d.m : (tile.trig == LSP_TRIG_DIRECT ? 1 : 8);
+        if (tile.waves == 0) tile.waves = d.waves;
+    }
+    if (tile.splits == 0) tile.splits = heuristic_splits(Nt, Nf, tile.m, di->cus);
+    if (!pgram_tile_supported(phase, tile)) {
+        g_last_error = "launch shape not built into the library";
+        return LSP_ERR_UNSUPPORTED;
+    }
+    int64_t chunk = 0;
+    int eff = 1;
+    split_geometry(Nt, tile.splits, &chunk, &eff);
+    tile.splits = eff;
+
+    const int n_mom = moment_blocks(Nt);
+    const Layout L = layout(Nt, Nf, tile.splits, n_mom);
+    StreamCtx &sc = stream_ctx(dev, s);
+    st = ensure(sc.ws, L.total, s);
+    if (st != LSP_OK) return st;
+    char *base = (char *)sc.ws.ptr;
+    Records rec;
+    rec.th = (float *)(base + L.th);
+    rec.tl = (float *)(base + L.tl);
+    rec.xv = (float *)(base + L.xv);
+    rec.rc = (float *)(base + L.rc);
+    rec.rs = (float *)(base + L.rs);
+    CurveStats *stats = (CurveStats *)(base + L.stats);
+    hipError_t e = launch_prep(t, x, Nt, (double)kWave * df, phase, (Moments *)(base + L.moments), n_mom,
+                               stats, rec, s);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+
+    PgramArgs a;
+    a.rec = rec;
+    a.stats = stats;
+    a.Nt = Nt;
+    a.chunk = chunk;
+    a.f_min = f_min;
+    a.df = df;
+    a.Nf = Nf;
+    a.Pn = Pn;
+    a.part = (double *)(base + L.part);
+    a.splits = tile.splits;
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (allow_profile && ctx().prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return hip_fail(hipGetLastError(), "hipEventCreate");
+        ctx().prof_events.emplace_back(ev0, ev1);
+        ctx().prof_name = pgram_kernel_name(phase, tile);
+    }
+    e = launch_pgram(a, phase, tile, s, ev0, ev1);
+    if (e != hipSuccess) return hip_fail(e, "periodogram launch");
+    if (stats_out) *stats_out = stats;
+    return LSP_OK;
+}
+
+lsp_status run_single_timed(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                            int64_t Nf, float *Pn, hipStream_t s, int phase, const lsp_tile &tile)
+{
+    return run_single(t, x, Nt, f_min, df, Nf, Pn, s, phase, tile, nullptr, false);
+}
+
+int device_cus()
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    if (device_info(&dev, &di) != LSP_OK) return 0;
+    return di->cus;
+}
+
+std::string device_arch()
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    if (device_info(&dev, &di) != LSP_OK) return "";
+    return di->arch;
+}
+
+void set_last_error(const std::string &m) { g_last_error = m; }
+
+// ---- batched -------------------------------------------------------------------------
+
+namespace {
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n)
+{
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct BatchLayout {
+    size_t stats, curves, items, queue, key, tbeg, tend, t0, th, tl, xv, rc, rs, total;
+};
+
+BatchLayout batch_layout(int64_t n, int64_t n_items, int64_t total_nt)
+{
+    BatchLayout L;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    L.stats = take(sizeof(CurveStats) * n);
+    L.curves = take(sizeof(BatchCurve) * n);
+    L.items = take(sizeof(BatchItem) * n_items);
+    L.queue = take(sizeof(uint32_t));
+    L.key = take(8 * n);
+    L.tbeg = take(8 * n);
+    L.tend = take(8 * n);
+    L.t0 = take(8);
+    L.th = take(4 * total_nt);
+    L.tl = take(4 * total_nt);
+    L.xv = take(4 * total_nt);
+    L.rc = take(4 * total_nt);
+    L.rs = take(4 * total_nt);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+static lsp_status batched_impl(const double *t, const float *x, const int64_t *off, int32_t n,
+                               const double *f_min, const double *df, const int64_t *Nf, float *Pn,
+                               float *pmax, int64_t *kbest, double *fbest, uint64_t *t_ns, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    lsp_status st = device_info(&dev, &di);
+    if (st != LSP_OK) return st;
+    const int M = batched_m();
+    const int64_t per_wave = (int64_t)kWave * M;
+
+    // plan key: everything that shapes the graph
+    uint64_t key = 1469598103934665603ull;
+    key = fnv1a(key, &n, sizeof(n));
+    key = fnv1a(key, off, sizeof(int64_t) * (size_t)(n + 1));
+    key = fnv1a(key, f_min, sizeof(double) * (size_t)n);
+    key = fnv1a(key, df, sizeof(double) * (size_t)n);
+    key = fnv1a(key, Nf, sizeof(int64_t) * (size_t)n);
+    const void *ptrs[] = {t, x, Pn, pmax, kbest, fbest, t_ns};
+    const uint64_t plan_key = key;
+    key = fnv1a(key, ptrs, sizeof(ptrs));
+
+    StreamCtx &sc = stream_ctx(dev, s);
+    const bool capturing = stream_capturing(s);
+
+    // fast path: same shape and pointers as the cached graph
+    if (!capturing && sc.graph.exec && sc.graph.key == key) {
+        hipError_t e = hipGraphLaunch(sc.graph.exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        return LSP_OK;
+    }
+
+    std::vector<BatchCurve> curves((size_t)n);
+    std::vector<BatchItem> items;
+    int64_t pn_off = 0;
+    for (int32_t c = 0; c < n; ++c) {
+        BatchCurve &cv = curves[(size_t)c];
+        cv.off = off[c];
+        cv.Nt = off[c + 1] - off[c];
+        cv.Nf = Nf[c];
+        cv.pn_off = pn_off;
+        cv.f_min = f_min[c];
+        cv.df = df[c];
+        pn_off += Nf[c];
+        const int64_t nfb = (Nf[c] + per_wave - 1) / per_wave;
+        for (int64_t b = 0; b < nfb; ++b) items.push_back(BatchItem{c, (int32_t)b});
+    }
+    // longest-processing-time first: every item of curve c costs ~Nt_c * 64 M terms
+    std::stable_sort(items.begin(), items.end(), [&](const BatchItem &a, const BatchItem &b) {
+        return curves[(size_t)a.curve].Nt > curves[(size_t)b.curve].Nt;
+    });
+    const int64_t total_nt = off[n];
+    const BatchLayout L = batch_layout(n, (int64_t)items.size(), total_nt);
+
+    if (capturing) {
+        // launched into the caller's capture: the plan must already be resident
+        if (sc.plan_key != plan_key || sc.bws.size < L.total) {
+            g_last_error = "batch shape not prepared before capture";
+            return LSP_ERR_CAPTURE;
+        }
+    } else if (sc.plan_key != plan_key || sc.bws.size < L.total) {
+        st = ensure(sc.bws, L.total, s);
+        if (st != LSP_OK) return st;
+        char *b = (char *)sc.bws.ptr;
+        hipError_t e = hipMemcpyAsync(b + L.curves, curves.data(), sizeof(BatchCurve) * curves.size(),
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !items.empty())
+            e = hipMemcpyAsync(b + L.items, items.data(), sizeof(BatchItem) * items.size(),
+                               hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors die with this call
+        if (e != hipSuccess) return hip_fail(e, "batch plan upload");
+        sc.plan_key = plan_key;
+    }
+
+    char *b = (char *)sc.bws.ptr;
+    BatchArgs a;
+    a.rec.th = (float *)(b + L.th);
+    a.rec.tl = (float *)(b + L.tl);
+    a.rec.xv = (float *)(b + L.xv);
+    a.rec.rc = (float *)(b + L.rc);
+    a.rec.rs = (float *)(b + L.rs);
+    a.stats = (CurveStats *)(b + L.stats);
+    a.curves = (const BatchCurve *)(b + L.curves);
+    a.items = (const BatchItem *)(b + L.items);
+    a.n_items = (int32_t)items.size();
+    a.n_curves = n;
+    a.queue = (uint32_t *)(b + L.queue);
+    a.key = (unsigned long long *)(b + L.key);
+    a.tbeg = (unsigned long long *)(b + L.tbeg);
+    a.tend = (unsigned long long *)(b + L.tend);
+    a.t0 = (unsigned long long *)(b + L.t0);
+    a.Pn = Pn;
+    a.pmax = pmax;
+    a.kbest = kbest;
+    a.fbest = fbest;
+    a.t_ns = t_ns;
+    a.t = t;
+    a.x = x;
+
+    const int waves = 4;
+    int per_cu = 0;
+    hipError_t e = batched_occupancy(waves, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    const int blocks = std::max(1, per_cu) * di->cus;
+
+    if (capturing || s == nullptr) {
+        e = launch_batched(a, M, blocks, waves, s);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+        return LSP_OK;
+    }
+    // capture once, replay afterwards
+    if (sc.graph.exec) {
+        hipGraphExecDestroy(sc.graph.exec);
+        hipGraphDestroy(sc.graph.graph);
+        sc.graph = BatchGraph();
+    }
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t el = launch_batched(a, M, blocks, waves, s);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(s, &g);
+    if (el != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_fail(el, "batched launch (capture)");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    sc.graph.key = key;
+    sc.graph.graph = g;
+    sc.graph.exec = ex;
+    e = hipGraphLaunch(ex, s);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return LSP_OK;
+}
+
+}  // namespace lsp
+
+using namespace lsp;
+
+// =====================================================================================
+// C ABI
+
+extern "C" {
+
+const char *lsp_status_string(lsp_status s)
+{
+    switch (s) {
+    case LSP_OK: return "ok";
+    case LSP_ERR_INVALID_ARG: return "invalid argument";
+    case LSP_ERR_ZERO_VARIANCE: return "zero variance (constant series)";
+    case LSP_ERR_NO_DEVICE: return "no gfx950 device";
+    case LSP_ERR_HIP: return "HIP runtime error";
+    case LSP_ERR_MODEL: return "surrogate model error";
+    case LSP_ERR_CAPTURE: return "not allowed during stream capture";
+    case LSP_ERR_UNSUPPORTED: return "unsupported option";
+    }
+    return "unknown status";
+}
+
+const char *lsp_last_error(void) { return g_last_error.c_str(); }
+
+const char *lsp_version(void) { return "mi355lsp 0.1.0"; }
+
+int32_t lsp_device_count(void)
+{
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+    int good = 0;
+    for (int d = 0; d < n; ++d) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, d) == hipSuccess && std::string(p.gcnArchName).rfind("gfx950", 0) == 0)
+            ++good;
+    }
+    return good;
+}
+
+lsp_status lsp_grid_paper(double t_min, double t_max, int64_t Nt, double F_over, double F_high,
+                          int32_t round_to, double *f_min, double *df, int64_t *Nf)
+{
+    if (!f_min || !df || !Nf) return LSP_ERR_INVALID_ARG;
+    if (!std::isfinite(t_min) || !std::isfinite(t_max) || !(t_max > t_min) || Nt < 2 ||
+        !finite_pos(F_over) || !finite_pos(F_high) || round_to < 1)
+        return LSP_ERR_INVALID_ARG;
+    const double d = 1.0 / (F_over * (t_max - t_min));  // Eq. (10)
+    const double nf = std::ceil(F_high * F_over * (double)Nt / 2.0 - 1e-9);  // Eq. (11)
+    if (!finite_pos(d) || !(nf >= 1.0) || nf > 9e15) return LSP_ERR_INVALID_ARG;
+    int64_t n = (int64_t)nf;
+    n = (n + round_to - 1) / round_to * round_to;
+    *df = d;
+    *f_min = d;  // Eq. (9): f_i = i df, i = 1..Nf
+    *Nf = n;
+    return LSP_OK;
+}
+
+double lsp_fap_analytic(double Pn, int64_t Nt, int64_t Nf)
+{
+    if (Nt < 4 || Nf < 1 || !(Pn >= 0.0) || Pn > 0.5 * (double)Nt) return NAN;
+    // Eq. (3) as -expm1(Nf * log1p(-q)), q = (1 - 2Pn/Nt)^((Nt-3)/2)
+    const double lq = 0.5 * (double)(Nt - 3) * std::log1p(-2.0 * Pn / (double)Nt);
+    const double q = std::exp(lq);
+    if (q >= 1.0) return 1.0;
+    return -std::expm1((double)Nf * std::log1p(-q));
+}
+
+lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                              int64_t Nf, float *Pn, void *stream, const lsp_options *opt)
+{
+    g_last_error.clear();
+    if (!t || !x || !Pn || Nt < 2 || Nt > kMaxNt || Nf < 1 || Nf > kMaxNf || !finite_nonneg(f_min) ||
+        !finite_pos(df) || !std::isfinite(f_min + (double)(Nf - 1) * df)) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    lsp_options o;
+    std::memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    if (o.phase != LSP_PHASE_SPLIT && o.phase != LSP_PHASE_NAIVE && o.phase != LSP_PHASE_SPLIT32) {
+        g_last_error = "unknown phase mode";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (o.tile.trig != 0 && o.tile.trig != LSP_TRIG_DIRECT && o.tile.trig != LSP_TRIG_RECUR) {
+        g_last_error = "unknown trig mode";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (o.tile.m < 0 || o.tile.waves < 0 || o.tile.splits < 0) {
+        g_last_error = "negative launch-shape field";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (o.phase == LSP_PHASE_NAIVE && o.tile.trig == LSP_TRIG_RECUR) {
+        g_last_error = "the recurrence needs the split phase";
+        return LSP_ERR_UNSUPPORTED;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const CurveStats *stats = nullptr;
+    lsp_status st = run_single(t, x, Nt, f_min, df, Nf, Pn, s, o.phase, o.tile, &stats, true);
+    if (st != LSP_OK || !o.check) return st;
+    CurveStats h;
+    hipError_t e = hipMemcpyAsync(&h, stats, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "status read-back");
+    return h.zero_var ? LSP_ERR_ZERO_VARIANCE : LSP_OK;
+}
+
+lsp_status lsp_periodogram(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                           int64_t Nf, float *Pn, void *stream)
+{
+    return lsp_periodogram_ex(t, x, Nt, f_min, df, Nf, Pn, stream, nullptr);
+}
+
+lsp_status lsp_periodogram_batched(const double *t, const float *x, const int64_t *off, int32_t n_curves,
+                                   const double *f_min, const double *df, const int64_t *Nf, float *Pn,
+                                   float *pmax, int64_t *kbest, double *fbest, uint64_t *t_ns,
+                                   void *stream)
+{
+    g_last_error.clear();
+    if (!t || !x || !off || !f_min || !df || !Nf || !pmax || n_curves < 1 || off[0] != 0) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    int64_t total_nf = 0;
+    for (int32_t c = 0; c < n_curves; ++c) {
+        const int64_t nt = off[c + 1] - off[c];
+        if (nt < 2 || nt > kMaxNt || Nf[c] < 1 || Nf[c] > kMaxNf || !finite_nonneg(f_min[c]) ||
+            !finite_pos(df[c]) || !std::isfinite(f_min[c] + (double)(Nf[c] - 1) * df[c])) {
+            g_last_error = "invalid curve " + std::to_string(c);
+            return LSP_ERR_INVALID_ARG;
+        }
+        total_nf += Nf[c];
+    }
+    (void)total_nf;
+    return batched_impl(t, x, off, n_curves, f_min, df, Nf, Pn, pmax, kbest, fbest, t_ns,
+                        (hipStream_t)stream);
+}
+
+lsp_status lsp_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    for (auto &p : ctx().prof_events) {
+        hipEventDestroy(p.first);
+        hipEventDestroy(p.second);
+    }
+    ctx().prof_events.clear();
+    ctx().prof_name.clear();
+    ctx().prof = on != 0;
+    return LSP_OK;
+}
+
+lsp_status lsp_profile_read(double *total_ms, int64_t *launches, char *name, int32_t name_len)
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    double tot = 0.0;
+    for (auto &p : ctx().prof_events) {
+        hipError_t e = hipEventSynchronize(p.second);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.first, p.second);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)ctx().prof_events.size();
+    if (name && name_len > 0) {
+        std::strncpy(name, ctx().prof_name.c_str(), (size_t)name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    return LSP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+"""Host-side checks of the C ABI (CPU only: no kernel is launched)."""
+import ctypes
+import math
+import re
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import paper_1007_1658_amd as lsp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lsp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert "lsp_periodogram" in names and "lsp_periodogram_batched" in names
+    L = lsp.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    # and the binding covers the same surface
+    assert set(names) <= set(lsp.SIGNATURES)
+
+
+def test_status_strings():
+    for s in (0, -1, -2, -3, -4, -5, -6, -7):
+        assert lsp.lsp_status_string(s)
+    assert lsp.lsp_version().startswith("mi355lsp")
+
+
+def test_grid_helper_reproduces_paper_nf():
+    # CoRoT series of Section 5.2: Nt = 382,003; with oversampling 4, high factor 2 and the
+    # kernel's 256-thread blocks the printed Nf = 1,528,064 follows.
+    f_min, df, nf = lsp.lsp_grid_paper(0.0, 150.0, 382003, 4.0, 2.0, 256)
+    assert nf == 1528064
+    assert df == pytest.approx(1.0 / 600.0)
+    assert f_min == df
+    # no rounding: Nf = F_high F_over Nt / 2 exactly (Eq. (11)), c0 grid
+    f_min, df, nf = lsp.lsp_grid_paper(0.3, 99.8, 1000, 4.0, 1.0, 1)
+    assert nf == 2000 and df == pytest.approx(1.0 / (4 * 99.5))
+    # odd products round up
+    assert lsp.lsp_grid_paper(0, 1, 1001, 1.0, 1.0, 1)[2] == 501
+
+
+@pytest.mark.parametrize("bad", [
+    (1.0, 1.0, 10, 4, 1, 1), (0, 1, 1, 4, 1, 1), (0, 1, 10, 0, 1, 1), (0, 1, 10, 4, -1, 1),
+    (0, 1, 10, 4, 1, 0), (0, float("inf"), 10, 4, 1, 1),
+])
+def test_grid_helper_rejects(bad):
+    with pytest.raises(lsp.LspError) as ei:
+        lsp.lsp_grid_paper(*bad)
+    assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
+
+
+def test_fap_analytic_against_oracle_and_beta():
+    for Nt in (4, 10, 1000, 65536):
+        for Nf in (1, 2000, 131072):
+            for P in np.linspace(0, Nt / 2, 9):
+                a = lsp.lsp_fap_analytic(P, Nt, Nf)
+                b = oracle.fap(P, Nt, Nf)
+                assert a == pytest.approx(b, rel=1e-12, abs=1e-300)
+    assert lsp.lsp_fap_analytic(2.0, 100, 1) == pytest.approx(stats.beta(1, 48.5).sf(0.04), rel=1e-10)
+    assert math.isnan(lsp.lsp_fap_analytic(1.0, 3, 5))
+    assert math.isnan(lsp.lsp_fap_analytic(-1.0, 30, 5))
+    assert math.isnan(lsp.lsp_fap_analytic(16.0, 30, 5))
+
+
+def test_validation_happens_before_any_gpu_work():
+    L = lsp.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(16)  # never dereferenced: validation fails first
+    cases = [
+        (null, fake, 10, 0.1, 0.1, 10, fake),     # null t
+        (fake, fake, 1, 0.1, 0.1, 10, fake),      # Nt < 2
+        (fake, fake, 10, 0.1, 0.0, 10, fake),     # df = 0
+        (fake, fake, 10, -0.1, 0.1, 10, fake),    # f_min < 0
+        (fake, fake, 10, 0.1, 0.1, 0, fake),      # Nf = 0
+        (fake, fake, 10, float("nan"), 0.1, 10, fake),
+        (fake, fake, 10, 0.1, float("inf"), 10, fake),
+        (fake, fake, 10, 0.1, 0.1, 10, null),     # null Pn
+    ]
+    for c in cases:
+        assert L.lsp_periodogram(*c, null) == lsp.LSP_ERR_INVALID_ARG
+    # an unknown phase mode is rejected too
+    opt = lsp.lsp_options()
+    opt.phase = 9
+    assert L.lsp_periodogram_ex(fake, fake, 10, 0.1, 0.1, 10, fake, null, ctypes.byref(opt)) == \
+        lsp.LSP_ERR_INVALID_ARG
+    opt.phase = lsp.LSP_PHASE_NAIVE
+    opt.tile.trig = lsp.LSP_TRIG_RECUR
+    assert L.lsp_periodogram_ex(fake, fake, 10, 0.1, 0.1, 10, fake, null, ctypes.byref(opt)) == \
+        lsp.LSP_ERR_UNSUPPORTED
+
+
+def test_batched_validation_on_host():
+    L = lsp.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(16)
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    off = np.array([0, 5, 6], dtype=np.int64)      # second curve has Nt = 1
+    fm = np.array([0.1, 0.1])
+    df = np.array([0.1, 0.1])
+    nf = np.array([10, 10], dtype=np.int64)
+    assert L.lsp_periodogram_batched(fake, fake, hp(off), 2, hp(fm), hp(df), hp(nf), null, fake, null, null,
+                                     null, null) == lsp.LSP_ERR_INVALID_ARG
+    off = np.array([1, 5, 9], dtype=np.int64)      # off[0] != 0
+    assert L.lsp_periodogram_batched(fake, fake, hp(off), 2, hp(fm), hp(df), hp(nf), null, fake, null, null,
+                                     null, null) == lsp.LSP_ERR_INVALID_ARG
+
+
+def test_no_device_reported_without_gpu():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    assert lsp.lsp_device_count() == 0
+    L = lsp.lib()
+    fake = ctypes.c_void_p(16)
+    st = L.lsp_periodogram(fake, fake, 10, 0.1, 0.1, 10, fake, ctypes.c_void_p(0))
+    assert st == lsp.LSP_ERR_NO_DEVICE

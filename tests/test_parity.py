@@ -1,0 +1,191 @@
+"""GPU parity: the HIP periodogram against the FP64 oracle (needs a gfx950 GPU).
+
+Bar: max|dPn| / max(Pn_oracle) <= 1e-4 and the same peak bin (or an oracle
+near-tie within that tolerance), on the same seeded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1007_1658_amd import synth
+from util import REL_TOL, peak_matches, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1007_1658_amd as lsp  # noqa: E402
+
+# every launch shape built into the library, per phase mode
+SPLIT_SHAPES = [("recur", m) for m in (4, 8, 12, 16)] + [("direct", m) for m in (1, 2, 4)]
+SPLIT32_SHAPES = [("recur", 8), ("recur", 16), ("direct", 1), ("direct", 4)]
+NAIVE_SHAPES = [("direct", 1), ("direct", 2), ("direct", 4)]
+ALL = ([("split",) + s for s in SPLIT_SHAPES] + [("split32",) + s for s in SPLIT32_SHAPES]
+       + [("naive",) + s for s in NAIVE_SHAPES])
+
+
+@pytest.fixture(scope="module")
+def c0_case():
+    c = synth.c0()
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=c.Nf)
+    return c, P
+
+
+@pytest.mark.parametrize("phase,trig,m", ALL)
+@pytest.mark.parametrize("waves,splits", [(4, 1), (2, 3)])
+def test_c0_all_shapes(c0_case, phase, trig, m, waves, splits):
+    c, P = c0_case
+    print(f"c0 phase={phase} trig={trig} m={m} waves={waves} splits={splits}", flush=True)
+    t, x = to_dev(c)
+    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, phase=phase, trig=trig, m=m,
+                                waves=waves, splits=splits).cpu().numpy()
+    assert rel_err(Pg, P) <= REL_TOL
+    assert peak_matches(Pg, P)
+
+
+@pytest.mark.parametrize("Nt,Nf,splits", [
+    (2, 1, 1), (3, 7, 1), (63, 100, 1), (64, 64, 1), (65, 513, 2), (130, 1025, 3),
+    (1000, 511, 4), (4097, 3000, 5), (257, 8193, 1), (5000, 20, 64),
+])
+@pytest.mark.parametrize("phase,trig,m", [("split", "recur", 8), ("split", "recur", 16),
+                                          ("split", "direct", 1), ("split32", "recur", 8),
+                                          ("naive", "direct", 4)])
+def test_ragged_sizes(Nt, Nf, splits, phase, trig, m):
+    print(f"ragged Nt={Nt} Nf={Nf} splits={splits} {phase}/{trig}/{m}", flush=True)
+    g = np.random.default_rng([11, Nt, Nf])
+    tt = np.sort(g.uniform(0.0, 30.0, Nt))
+    xx = (np.sin(2 * np.pi * 1.3 * tt) + g.normal(0, 1.0, Nt)).astype(np.float32)
+    T = tt.max() - tt.min()
+    df = 1.0 / (4 * T)
+    c = synth.Curve(tt, xx, df, df, Nf)
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=Nf)
+    t, x = to_dev(c)
+    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, Nf, phase=phase, trig=trig, m=m,
+                                waves=4, splits=splits).cpu().numpy()
+    assert Pg.shape == (Nf,)
+    assert rel_err(Pg, P) <= REL_TOL
+    assert peak_matches(Pg, P)
+
+
+def test_default_call_and_output_fully_written(c0_case):
+    c, P = c0_case
+    t, x = to_dev(c)
+    Pn = torch.full((c.Nf + 7,), -1.0, dtype=torch.float32, device="cuda")
+    lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf, Pn=Pn)
+    Pg = Pn.cpu().numpy()
+    assert np.all(Pg[:c.Nf] >= 0.0)
+    assert np.all(Pg[c.Nf:] == -1.0)  # nothing past Nf is touched
+    assert rel_err(Pg[:c.Nf], P) <= REL_TOL
+
+
+def test_c1_full_size_sampled():
+    """Full c1 size in the benchmark's default launch; oracle on sampled bins."""
+    c = synth.c1()
+    t, x = to_dev(c)
+    print(f"c1 Nt={c.Nt} Nf={c.Nf}", flush=True)
+    Pg = lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf).cpu().numpy()
+    g = np.random.default_rng(1)
+    kpk = int(np.argmax(Pg))
+    k = np.unique(np.concatenate([g.integers(0, c.Nf, 600), np.arange(max(0, kpk - 8), min(c.Nf, kpk + 9)),
+                                  np.arange(0, 64), np.arange(c.Nf - 64, c.Nf)]))
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, k=k)
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
+    print(f"c1 sampled rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert np.all(Pg >= 0) and np.all(Pg <= c.Nt / 2 * (1 + 1e-5))
+    # the global peak is one of the injected frequencies (within one bin)
+    f_pk = c.f_min + kpk * c.df
+    assert np.min(np.abs(c.injected - f_pk)) <= 1.5 * c.df
+
+
+def test_c2_precision_split_vs_naive():
+    """Epoch-offset times (2455000 d + 3650 d): the split path meets the bar, the naive one does not."""
+    c = synth.c2()
+    t, x = to_dev(c)
+    print(f"c2 Nt={c.Nt} Nf={c.Nf}", flush=True)
+    Ps = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, phase="split").cpu().numpy()
+    k0 = int(round((13.7 - c.f_min) / c.df))
+    g = np.random.default_rng(2)
+    k = np.unique(np.concatenate([g.integers(0, c.Nf, 300), np.arange(k0 - 6, k0 + 7)]))
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, k=k)
+    err_s = float(np.max(np.abs(Ps[k] - P)) / P.max())
+    assert abs(int(np.argmax(Ps)) - k0) <= 1
+    Pn = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, phase="naive", trig="direct", m=4).cpu().numpy()
+    err_n = float(np.max(np.abs(Pn[k] - P)) / P.max())
+    print(f"c2 sampled rel err split {err_s:.3e} naive {err_n:.3e}", flush=True)
+    assert err_s <= REL_TOL
+    assert err_n > 10 * err_s
+
+
+def test_deterministic_rerun():
+    c = synth.c1(Nt=20000, Nf=40000)
+    t, x = to_dev(c)
+    a = lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf).cpu().numpy()
+    b = lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_invariances_on_gpu():
+    c = synth.c0(Nt=3000, Nf=6000)
+    t, x = to_dev(c)
+    base = lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf).cpu().numpy()
+    m = base.max()
+    shifted = lsp.lsp_periodogram(t + 2455000.0, x, c.f_min, c.df, c.Nf).cpu().numpy()
+    assert np.max(np.abs(shifted - base)) <= REL_TOL * m
+    scaled = lsp.lsp_periodogram(t, (x * -4.5 + 3.0).contiguous(), c.f_min, c.df, c.Nf).cpu().numpy()
+    assert np.max(np.abs(scaled - base)) <= REL_TOL * m
+    p = torch.randperm(c.Nt, generator=torch.Generator().manual_seed(3)).cuda()
+    perm = lsp.lsp_periodogram(t[p].contiguous(), x[p].contiguous(), c.f_min, c.df, c.Nf).cpu().numpy()
+    assert np.max(np.abs(perm - base)) <= REL_TOL * m
+
+
+def test_zero_frequency_and_constant_series():
+    c = synth.c0(Nt=500, Nf=50)
+    t, x = to_dev(c)
+    Pg = lsp.lsp_periodogram(t, x, 0.0, c.df, c.Nf).cpu().numpy()   # k = 0 is f = 0
+    P = oracle.periodogram(c.t, c.x, 0.0, c.df, Nf=c.Nf)
+    assert abs(Pg[0]) <= REL_TOL * P.max()
+    assert rel_err(Pg, P) <= REL_TOL
+    xc = torch.full_like(x, 2.5)
+    Pc = lsp.lsp_periodogram(t, xc, c.f_min, c.df, c.Nf).cpu().numpy()
+    assert np.all(Pc == 0.0)
+    with pytest.raises(lsp.LspError) as ei:
+        lsp.lsp_periodogram_ex(t, xc, c.f_min, c.df, c.Nf, check=True)
+    assert ei.value.status == lsp.LSP_ERR_ZERO_VARIANCE
+
+
+def test_profile_hook_counts_launches():
+    c = synth.c0()
+    t, x = to_dev(c)
+    lsp.lsp_profile_enable(True)
+    for _ in range(3):
+        lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf)
+    ms, n, name = lsp.lsp_profile_read()
+    lsp.lsp_profile_enable(False)
+    assert n == 3 and ms > 0 and name.startswith("pgram_kernel")
+
+
+def test_autotune_and_cache_roundtrip(tmp_path):
+    tile, ms = lsp.lsp_autotune(4096, 8192)
+    assert tile["m"] > 0 and ms > 0
+    c = synth.c0(Nt=4096, Nf=8192)
+    t, x = to_dev(c)
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, k=np.arange(0, 8192, 37))
+    Pg = lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf).cpu().numpy()  # uses the tuned shape
+    assert float(np.max(np.abs(Pg[::37] - P)) / P.max()) <= REL_TOL
+    f = tmp_path / "tune.json"
+    lsp.lsp_tune_cache_save(str(f))
+    lsp.lsp_tune_cache_load(str(f))
+    assert "mi355lsp-tune-1" in f.read_text()
+
+
+def test_invalid_arguments_raise():
+    c = synth.c0(Nt=100, Nf=10)
+    t, x = to_dev(c)
+    for bad in [dict(df=0.0), dict(df=-1.0), dict(Nf=0), dict(f_min=float("nan"))]:
+        kw = dict(f_min=c.f_min, df=c.df, Nf=c.Nf)
+        kw.update(bad)
+        with pytest.raises((lsp.LspError, RuntimeError)):
+            lsp.lsp_periodogram(t, x, kw["f_min"], kw["df"], kw["Nf"])
