@@ -77,13 +77,24 @@ typedef enum lsp_trig_mode {
     LSP_TRIG_RECUR = 2
 } lsp_trig_mode;
 
-/* Launch shape of the periodogram kernel.  All-zero = library's choice. */
+/* How each lane's FP32 partial sums (kept over groups of 256 samples) are
+   folded into its totals. */
+typedef enum lsp_sum_mode {
+    LSP_SUM_AUTO = 0,
+    LSP_SUM_KAHAN = 1,  /* Kahan-compensated FP32 totals */
+    LSP_SUM_TWO = 2     /* plain FP32 totals (two-level summation) */
+} lsp_sum_mode;
+
+/* Launch shape of the periodogram kernel.  A zero field = library's choice
+   (tuner cache, else heuristic).  lsp_autotune lists what is built. */
 typedef struct lsp_tile {
     int32_t trig;   /* lsp_trig_mode */
-    int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4,8,12,16 */
-    int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2, 4 or 8 */
+    int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4..24 */
+    int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2 or 4 */
     int32_t splits; /* workgroups sharing one frequency block along the sample
                        axis (1 = none); partials merged in fixed order in FP64 */
+    int32_t unroll; /* samples per broadcast LDS read group: 1, 2 or 4 */
+    int32_t sum;    /* lsp_sum_mode */
 } lsp_tile;
 
 typedef struct lsp_options {
@@ -159,9 +170,30 @@ lsp_status lsp_periodogram_batched(const double *t, const float *x,
    same buckets with an all-zero tile use it.  best_ms may be NULL. */
 lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream,
                         lsp_tile *best, double *best_ms);
+/* The launch shapes built into the library for a phase mode (waves and
+   splits are 0 in the listing: any of 1, 2, 4 waves and any split count work).
+   Writes at most cap entries to out (out may be NULL) and returns how many
+   exist, or -1 for an unknown phase mode.  Host-only. */
+int32_t lsp_list_tiles(int32_t phase, lsp_tile *out, int32_t cap);
+
+/* The cached shape for (Nt, Nf, phase) on the current device, if any:
+   LSP_OK and *tile filled, or LSP_ERR_INVALID_ARG when nothing is cached
+   (or tile is NULL), LSP_ERR_NO_DEVICE without a gfx950 device. */
+lsp_status lsp_tune_lookup(int64_t Nt, int64_t Nf, int32_t phase, lsp_tile *tile);
 /* JSON persistence of the tuner cache; path NULL = $LSP_TUNE_CACHE. */
 lsp_status lsp_tune_cache_save(const char *path);
 lsp_status lsp_tune_cache_load(const char *path);
+
+/* ---- microbenchmarks --------------------------------------------------------------
+
+   Measures one instruction class on the current device with eight
+   independent chains per lane and `waves_per_simd` resident waves:
+   kind 0 FP32 FMA, 1 FP64 FMA, 2 hardware sin+cos pair, 3 FP64 phase
+   reduction (multiply, round to nearest, subtract, convert to FP32).
+   Synchronous on `stream`.  *ops_per_s = lane-operations per second;
+   ms may be NULL. */
+lsp_status lsp_microbench(int32_t kind, int32_t waves_per_simd, int32_t iters,
+                          void *stream, double *ops_per_s, double *ms);
 
 /* ---- profiling hook ------------------------------------------------------------
 

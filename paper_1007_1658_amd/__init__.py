@@ -46,12 +46,20 @@ class LspError(RuntimeError):
         super().__init__(msg)
 
 
+LSP_SUM_AUTO = 0
+LSP_SUM_KAHAN = 1
+LSP_SUM_TWO = 2
+SUMS = {"auto": LSP_SUM_AUTO, "kahan": LSP_SUM_KAHAN, "two": LSP_SUM_TWO}
+
+
 class lsp_tile(ctypes.Structure):
     _fields_ = [("trig", ctypes.c_int32), ("m", ctypes.c_int32),
-                ("waves", ctypes.c_int32), ("splits", ctypes.c_int32)]
+                ("waves", ctypes.c_int32), ("splits", ctypes.c_int32),
+                ("unroll", ctypes.c_int32), ("sum", ctypes.c_int32)]
 
     def as_dict(self):
-        return {"trig": self.trig, "m": self.m, "waves": self.waves, "splits": self.splits}
+        return {"trig": self.trig, "m": self.m, "waves": self.waves, "splits": self.splits,
+                "unroll": self.unroll, "sum": self.sum}
 
 
 class lsp_options(ctypes.Structure):
@@ -70,8 +78,11 @@ SIGNATURES = {
     "lsp_periodogram_ex": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P, ctypes.POINTER(lsp_options)]),
     "lsp_periodogram_batched": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lsp_autotune": (_I32, [_I64, _I64, _I32, _P, ctypes.POINTER(lsp_tile), ctypes.POINTER(_D)]),
+    "lsp_tune_lookup": (_I32, [_I64, _I64, _I32, ctypes.POINTER(lsp_tile)]),
+    "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
     "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
     "lsp_tune_cache_load": (_I32, [ctypes.c_char_p]),
+    "lsp_microbench": (_I32, [_I32, _I32, _I32, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "lsp_profile_enable": (_I32, [_I32]),
     "lsp_profile_read": (_I32, [ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.c_char_p, _I32]),
     "lsp_grid_paper": (_I32, [_D, _D, _I64, _D, _D, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -173,7 +184,8 @@ def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None
 
 
 def lsp_periodogram_ex(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None,
-                       phase="split", trig="auto", m=0, waves=0, splits=0, check=False):
+                       phase="split", trig="auto", m=0, waves=0, splits=0, unroll=0, sum="auto",
+                       check=False):
     torch = _torch()
     _dev_tensor(t, torch.float64, "t")
     _dev_tensor(x, torch.float32, "x")
@@ -189,6 +201,8 @@ def lsp_periodogram_ex(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=N
     opt.check = 1 if check else 0
     opt.tile.trig = TRIGS[trig] if isinstance(trig, str) else int(trig)
     opt.tile.m, opt.tile.waves, opt.tile.splits = int(m), int(waves), int(splits)
+    opt.tile.unroll = int(unroll)
+    opt.tile.sum = SUMS[sum] if isinstance(sum, str) else int(sum)
     with torch.cuda.device(t.device):
         st = lib().lsp_periodogram_ex(_ptr(t), _ptr(x), t.numel(), float(f_min), float(df), int(Nf),
                                       _ptr(Pn), _stream_ptr(stream), ctypes.byref(opt))
@@ -248,12 +262,45 @@ def lsp_autotune(Nt: int, Nf: int, phase="split", stream=None):
     return tile.as_dict(), ms.value
 
 
+def lsp_list_tiles(phase="split"):
+    """The launch shapes built into the library for a phase mode (list of dicts)."""
+    ph = PHASES[phase] if isinstance(phase, str) else int(phase)
+    n = lib().lsp_list_tiles(ph, None, 0)
+    if n < 0:
+        raise LspError(LSP_ERR_INVALID_ARG, "lsp_list_tiles")
+    arr = (lsp_tile * max(n, 1))()
+    lib().lsp_list_tiles(ph, arr, n)
+    return [arr[i].as_dict() for i in range(n)]
+
+
+def lsp_tune_lookup(Nt: int, Nf: int, phase="split"):
+    """The cached launch shape for (Nt, Nf, phase) as a dict, or None."""
+    tile = lsp_tile()
+    ph = PHASES[phase] if isinstance(phase, str) else int(phase)
+    st = lib().lsp_tune_lookup(int(Nt), int(Nf), ph, ctypes.byref(tile))
+    if st == LSP_ERR_INVALID_ARG:
+        return None
+    _check(st, "lsp_tune_lookup")
+    return tile.as_dict()
+
+
+TUNE_CACHE = os.path.join(_HERE, "tune_gfx950.json")
+
+
 def lsp_tune_cache_save(path=None):
     _check(lib().lsp_tune_cache_save(path.encode() if path else None), "lsp_tune_cache_save")
 
 
 def lsp_tune_cache_load(path=None):
     _check(lib().lsp_tune_cache_load(path.encode() if path else None), "lsp_tune_cache_load")
+
+
+def lsp_microbench(kind: int, waves_per_simd: int = 2, iters: int = 4096, stream=None):
+    """(lane-ops/s, ms) of one instruction class: 0 FP32 FMA, 1 FP64 FMA, 2 sin+cos, 3 FP64 phase."""
+    ops, ms = _D(), _D()
+    _check(lib().lsp_microbench(int(kind), int(waves_per_simd), int(iters), _stream_ptr(stream),
+                                ctypes.byref(ops), ctypes.byref(ms)), "lsp_microbench")
+    return ops.value, ms.value
 
 
 def lsp_profile_enable(on: bool = True):

@@ -5,14 +5,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/lsp.h"
 
 namespace lsp {
 
 constexpr int kWave = 64;          // gfx950 wavefront width
-constexpr int kMaxWaves = 8;       // waves per workgroup supported by the kernels
+constexpr int kMaxWaves = 4;       // waves per workgroup supported by the kernels
 constexpr int kTile = 64;          // samples staged per wave per tile (one per lane)
-constexpr int kFoldTiles = 4;      // tiles between compensated folds of the FP32 partials
+constexpr int kFoldTiles = 8;      // tiles between compensated folds of the FP32 partials
 
 // Per-curve scalars written by the prep kernels and read by the rest.
 struct CurveStats {
@@ -47,8 +49,8 @@ struct PgramArgs {
     int64_t chunk;      // samples per split (multiple of kTile)
     double f_min, df;
     int64_t Nf;
-    float *Pn;          // written when splits == 1
-    double *part;       // [splits][4][Nf] FP64 partial sums when splits > 1
+    float *Pn;          // output, written by the reduce/epilogue kernel
+    float *part;        // [splits][4][Nf] per-chunk sums (merged in FP64)
     int32_t splits;
 };
 
@@ -95,10 +97,17 @@ hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hip
                         hipEvent_t ev0, hipEvent_t ev1);
 const char *pgram_kernel_name(int phase, const lsp_tile &tile);
 bool pgram_tile_supported(int phase, const lsp_tile &tile);
+void pgram_complete_tile(int phase, lsp_tile &tile);
+int pgram_list_tiles(int phase, lsp_tile *out, int cap);
+hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu);
 
 hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,
                           hipStream_t s);
 int batched_m();
 hipError_t batched_occupancy(int waves, int *blocks_per_cu);
+
+// records a message for lsp_last_error() on this host thread (lsp_host.cpp)
+void set_last_error(const char *msg);
+void set_last_error(const std::string &msg);
 
 }  // namespace lsp

@@ -168,7 +168,7 @@ Layout layout(int64_t Nt, int64_t Nf, int splits, int n_mom)
     L.rs = o;
     o += fb;
     L.part = o;
-    if (splits > 1) o = align_up(o + sizeof(double) * 4 * (size_t)Nf * (size_t)splits);
+    o = align_up(o + sizeof(float) * 4 * (size_t)Nf * (size_t)splits);
     L.total = o;
     return L;
 }
@@ -179,18 +179,36 @@ int moment_blocks(int64_t Nt) { return (int)std::min<int64_t>(256, std::max<int6
 
 // ---- launch-shape choice -------------------------------------------------------------
 
-int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus)
+// Split count along the sample axis.  Resident workgroup slots come from the
+// occupancy of the variant; the cost model counts dispatch rounds times the
+// samples per wave (plus a fixed per-wave overhead), so that the last round is
+// not a nearly empty one.  blocks_per_cu <= 0: assume two workgroups per CU.
+int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus, int waves, int blocks_per_cu)
 {
+    if (waves < 1) waves = 4;
+    if (blocks_per_cu <= 0) blocks_per_cu = 2;
     const int64_t per_wave = (int64_t)kWave * m;
     const int64_t nfb = (Nf + per_wave - 1) / per_wave;
-    const int64_t target = (int64_t)cus * 16;  // about four waves per SIMD
-    int64_t s = (target + nfb - 1) / nfb;
-    const int64_t by_len = std::max<int64_t>(1, Nt / 256);  // at least 256 samples per split
-    s = std::min<int64_t>(s, by_len);
-    s = std::min<int64_t>(s, 64);
-    // keep the FP64 partials under 1 GiB
-    while (s > 1 && (double)s * 32.0 * (double)Nf > (double)(1u << 30)) --s;
-    return (int)std::max<int64_t>(1, s);
+    const int64_t fwg = (nfb + waves - 1) / waves;
+    const int64_t slots = (int64_t)cus * blocks_per_cu;
+    int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, Nt / 256));
+    // keep the per-chunk partial sums under 1 GiB
+    while (smax > 1 && (double)smax * 16.0 * (double)Nf > (double)(1u << 30)) --smax;
+    int64_t best_s = 1;
+    double best_cost = 1e300;
+    for (int64_t s = 1; s <= smax; ++s) {
+        int64_t chunk = (Nt + s - 1) / s;
+        chunk = (chunk + kTile - 1) / kTile * kTile;
+        const int64_t eff = (Nt + chunk - 1) / chunk;
+        const int64_t wgs = fwg * eff;
+        const int64_t rounds = (wgs + slots - 1) / slots;
+        const double cost = (double)rounds * (double)(chunk + 64) + 2.0 * (double)eff;
+        if (cost < best_cost * 0.999) {
+            best_cost = cost;
+            best_s = eff;
+        }
+    }
+    return (int)best_s;
 }
 
 lsp_tile default_tile(int phase, int64_t Nt, int64_t Nf, int cus)
@@ -199,12 +217,15 @@ lsp_tile default_tile(int phase, int64_t Nt, int64_t Nf, int cus)
     if (phase == LSP_PHASE_NAIVE) {
         t.trig = LSP_TRIG_DIRECT;
         t.m = 1;
+        t.sum = LSP_SUM_TWO;
     } else {
         t.trig = LSP_TRIG_RECUR;
         t.m = 8;
+        t.sum = LSP_SUM_KAHAN;
     }
+    t.unroll = 4;
     t.waves = 4;
-    t.splits = heuristic_splits(Nt, Nf, t.m, cus);
+    t.splits = heuristic_splits(Nt, Nf, t.m, cus, t.waves, 0);
     return t;
 }
 
@@ -227,20 +248,29 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     DeviceInfo *di = nullptr;
     lsp_status st = device_info(&dev, &di);
     if (st != LSP_OK) return st;
-    if (tile.trig == 0 || tile.m == 0 || tile.waves == 0) {
+    if (tile.trig == 0 || tile.m == 0 || tile.waves == 0 || tile.unroll == 0 || tile.sum == 0) {
         lsp_tile tuned;
-        if (tuner_lookup(di->arch, di->cus, phase, Nt, Nf, &tuned)) {
+        if (tuner_lookup(di->arch, di->cus, phase, Nt, Nf, &tuned) &&
+            (tile.trig == 0 || tile.trig == tuned.trig) && (tile.m == 0 || tile.m == tuned.m)) {
             if (tile.trig == 0) tile.trig = tuned.trig;
             if (tile.m == 0) tile.m = tuned.m;
             if (tile.waves == 0) tile.waves = tuned.waves;
             if (tile.splits == 0) tile.splits = tuned.splits;
+            if (tile.unroll == 0) tile.unroll = tuned.unroll;
+            if (tile.sum == 0) tile.sum = tuned.sum;
         }
-        lsp_tile d = default_tile(phase, Nt, Nf, di->cus);
+        const lsp_tile d = default_tile(phase, Nt, Nf, di->cus);
         if (tile.trig == 0) tile.trig = d.trig;
         if (tile.m == 0) tile.m = (tile.trig == d.trig) ? d.m : (tile.trig == LSP_TRIG_DIRECT ? 1 : 8);
         if (tile.waves == 0) tile.waves = d.waves;
+        if (tile.sum == 0 && tile.trig == d.trig && tile.m == d.m) tile.sum = d.sum;
+        pgram_complete_tile(phase, tile);
     }
-    if (tile.splits == 0) tile.splits = heuristic_splits(Nt, Nf, tile.m, di->cus);
+    if (tile.splits == 0) {
+        int per_cu = 0;
+        if (pgram_occupancy(phase, tile, &per_cu) != hipSuccess) per_cu = 0;
+        tile.splits = heuristic_splits(Nt, Nf, tile.m, di->cus, tile.waves, per_cu);
+    }
     if (!pgram_tile_supported(phase, tile)) {
         g_last_error = "launch shape not built into the library";
         return LSP_ERR_UNSUPPORTED;
@@ -276,7 +306,7 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     a.df = df;
     a.Nf = Nf;
     a.Pn = Pn;
-    a.part = (double *)(base + L.part);
+    a.part = (float *)(base + L.part);
     a.splits = tile.splits;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -317,6 +347,7 @@ std::string device_arch()
 }
 
 void set_last_error(const std::string &m) { g_last_error = m; }
+void set_last_error(const char *m) { g_last_error = m ? m : ""; }
 
 // ---- batched -------------------------------------------------------------------------
 

@@ -12,10 +12,13 @@
 //   * per term the lane needs (cos, sin) of 2 pi f_k t'_j and four FMAs into
 //     XC, XS, CC, CS (SS = Nt - CC, Section 4.4);
 //   * FP32 partials are folded every kFoldTiles tiles into Kahan-compensated
-//     FP32 totals; the epilogue (tau by atan2, Eq. (5), 1/variance) is FP64;
+//     FP32 totals (their compensation terms wait in wave-private LDS, so they
+//     cost no registers) or, as an option, plain two-level FP32 totals; the
+//     epilogue (tau by atan2, Eq. (5), 1/variance) is FP64;
 //   * when Nf alone cannot fill 256 CUs the sample axis is split over the
-//     grid's y dimension and a second kernel adds the FP64 partials in fixed
-//     split order (deterministic).
+//     grid's y dimension; a second kernel adds the per-chunk sums (stored
+//     FP32) in FP64 in fixed split order (deterministic) and evaluates the
+//     FP64 epilogue.
 #include <math.h>
 
 #include "internal.h"
@@ -191,6 +194,10 @@ struct Staged {
     float th, tl, x, rc, rs;
 };
 
+// Lanes past the end of the range stage a neutral sample: t' = 0 and x = 0,
+// step angle 0.  Its phase is exactly 0 for every frequency, so it adds 0 to
+// XC, XS and CS and exactly 1 (up to the rounding of the FP32 sum) to CC; the
+// epilogue subtracts the number of such samples from CC.
 template <int PHASE>
 __device__ __forceinline__ void fetch(const Records &r, int64_t j, bool ok, Staged &s)
 {
@@ -202,6 +209,12 @@ __device__ __forceinline__ void fetch(const Records &r, int64_t j, bool ok, Stag
             s.rc = r.rc[j];
             s.rs = r.rs[j];
         }
+    } else {
+        s.th = 0.0f;
+        s.tl = 0.0f;
+        s.x = 0.0f;
+        s.rc = 1.0f;
+        s.rs = 0.0f;
     }
 }
 
@@ -315,75 +328,170 @@ __device__ __forceinline__ void sample_terms(float (&p)[4][M], const Freq<PHASE,
     }
 }
 
-template <int PHASE>
-__device__ __forceinline__ Smp read_smp(const Tile<PHASE> &T, int j)
+// U consecutive samples with broadcast reads (all lanes read one address)
+template <int PHASE, int U>
+__device__ __forceinline__ void read_smp(const Tile<PHASE> &T, int j, Smp (&s)[U])
 {
-    Smp s;
-    if constexpr (PHASE == PH_SPLIT) {
-        s.t = T.t[j];
-        s.x = T.x[j];
-        s.rc = T.rc[j];
-        s.rs = T.rs[j];
-    } else if constexpr (PHASE == PH_SPLIT32) {
-        s.th = T.th[j];
-        s.tl = T.tl[j];
-        s.x = T.x[j];
-        s.rc = T.rc[j];
-        s.rs = T.rs[j];
+    if constexpr (U == 4) {
+        if constexpr (PHASE == PH_SPLIT) {
+            const double2 t01 = *reinterpret_cast<const double2 *>(&T.t[j]);
+            const double2 t23 = *reinterpret_cast<const double2 *>(&T.t[j + 2]);
+            s[0].t = t01.x; s[1].t = t01.y; s[2].t = t23.x; s[3].t = t23.y;
+        } else if constexpr (PHASE == PH_SPLIT32) {
+            const float4 h = *reinterpret_cast<const float4 *>(&T.th[j]);
+            const float4 l = *reinterpret_cast<const float4 *>(&T.tl[j]);
+            s[0].th = h.x; s[1].th = h.y; s[2].th = h.z; s[3].th = h.w;
+            s[0].tl = l.x; s[1].tl = l.y; s[2].tl = l.z; s[3].tl = l.w;
+        } else {
+            const float4 h = *reinterpret_cast<const float4 *>(&T.t[j]);
+            s[0].th = h.x; s[1].th = h.y; s[2].th = h.z; s[3].th = h.w;
+        }
+        const float4 x = *reinterpret_cast<const float4 *>(&T.x[j]);
+        s[0].x = x.x; s[1].x = x.y; s[2].x = x.z; s[3].x = x.w;
+        if constexpr (PHASE != PH_NAIVE) {
+            const float4 c = *reinterpret_cast<const float4 *>(&T.rc[j]);
+            const float4 r = *reinterpret_cast<const float4 *>(&T.rs[j]);
+            s[0].rc = c.x; s[1].rc = c.y; s[2].rc = c.z; s[3].rc = c.w;
+            s[0].rs = r.x; s[1].rs = r.y; s[2].rs = r.z; s[3].rs = r.w;
+        }
+    } else if constexpr (U == 2) {
+        if constexpr (PHASE == PH_SPLIT) {
+            const double2 t01 = *reinterpret_cast<const double2 *>(&T.t[j]);
+            s[0].t = t01.x; s[1].t = t01.y;
+        } else if constexpr (PHASE == PH_SPLIT32) {
+            const float2 h = *reinterpret_cast<const float2 *>(&T.th[j]);
+            const float2 l = *reinterpret_cast<const float2 *>(&T.tl[j]);
+            s[0].th = h.x; s[1].th = h.y;
+            s[0].tl = l.x; s[1].tl = l.y;
+        } else {
+            const float2 h = *reinterpret_cast<const float2 *>(&T.t[j]);
+            s[0].th = h.x; s[1].th = h.y;
+        }
+        const float2 x = *reinterpret_cast<const float2 *>(&T.x[j]);
+        s[0].x = x.x; s[1].x = x.y;
+        if constexpr (PHASE != PH_NAIVE) {
+            const float2 c = *reinterpret_cast<const float2 *>(&T.rc[j]);
+            const float2 r = *reinterpret_cast<const float2 *>(&T.rs[j]);
+            s[0].rc = c.x; s[1].rc = c.y;
+            s[0].rs = r.x; s[1].rs = r.y;
+        }
     } else {
-        s.th = T.t[j];
-        s.x = T.x[j];
+        if constexpr (PHASE == PH_SPLIT) {
+            s[0].t = T.t[j];
+        } else if constexpr (PHASE == PH_SPLIT32) {
+            s[0].th = T.th[j];
+            s[0].tl = T.tl[j];
+        } else {
+            s[0].th = T.t[j];
+        }
+        s[0].x = T.x[j];
+        if constexpr (PHASE != PH_NAIVE) {
+            s[0].rc = T.rc[j];
+            s[0].rs = T.rs[j];
+        }
     }
-    return s;
 }
 
-// four consecutive samples with 128-bit broadcast reads
-template <int PHASE>
-__device__ __forceinline__ void read_smp4(const Tile<PHASE> &T, int j, Smp (&s)[4])
-{
-    if constexpr (PHASE == PH_SPLIT) {
-        const double2 t01 = *reinterpret_cast<const double2 *>(&T.t[j]);
-        const double2 t23 = *reinterpret_cast<const double2 *>(&T.t[j + 2]);
-        const float4 x = *reinterpret_cast<const float4 *>(&T.x[j]);
-        const float4 c = *reinterpret_cast<const float4 *>(&T.rc[j]);
-        const float4 r = *reinterpret_cast<const float4 *>(&T.rs[j]);
-        s[0].t = t01.x; s[1].t = t01.y; s[2].t = t23.x; s[3].t = t23.y;
-        s[0].x = x.x; s[1].x = x.y; s[2].x = x.z; s[3].x = x.w;
-        s[0].rc = c.x; s[1].rc = c.y; s[2].rc = c.z; s[3].rc = c.w;
-        s[0].rs = r.x; s[1].rs = r.y; s[2].rs = r.z; s[3].rs = r.w;
-    } else if constexpr (PHASE == PH_SPLIT32) {
-        const float4 h = *reinterpret_cast<const float4 *>(&T.th[j]);
-        const float4 l = *reinterpret_cast<const float4 *>(&T.tl[j]);
-        const float4 x = *reinterpret_cast<const float4 *>(&T.x[j]);
-        const float4 c = *reinterpret_cast<const float4 *>(&T.rc[j]);
-        const float4 r = *reinterpret_cast<const float4 *>(&T.rs[j]);
-        s[0].th = h.x; s[1].th = h.y; s[2].th = h.z; s[3].th = h.w;
-        s[0].tl = l.x; s[1].tl = l.y; s[2].tl = l.z; s[3].tl = l.w;
-        s[0].x = x.x; s[1].x = x.y; s[2].x = x.z; s[3].x = x.w;
-        s[0].rc = c.x; s[1].rc = c.y; s[2].rc = c.z; s[3].rc = c.w;
-        s[0].rs = r.x; s[1].rs = r.y; s[2].rs = r.z; s[3].rs = r.w;
-    } else {
-        const float4 h = *reinterpret_cast<const float4 *>(&T.t[j]);
-        const float4 x = *reinterpret_cast<const float4 *>(&T.x[j]);
-        s[0].th = h.x; s[1].th = h.y; s[2].th = h.z; s[3].th = h.w;
-        s[0].x = x.x; s[1].x = x.y; s[2].x = x.z; s[3].x = x.w;
-    }
-}
+// How the FP32 partials of a tile group become the wave's totals.
+//   SUM_KAHAN: Kahan-compensated FP32 totals in registers for the sums that
+//              cancel (XC, XS, CS), their compensation terms in wave-private
+//              LDS (touched only at folds); CC, a sum of squares, needs none;
+//   SUM_TWO:   plain FP32 totals (two-level summation, as the paper's chunks).
+enum { SUM_KAHAN = 1, SUM_TWO = 2 };
 
-// Kahan fold of the FP32 tile partials into the running totals
-template <int M>
-__device__ __forceinline__ void fold(float (&p)[4][M], float (&S)[4][M], float (&C)[4][M])
+// compensated accumulator slot of sum q (XC 0, XS 1, CS 3), -1 for CC
+__device__ __forceinline__ constexpr int comp_slot(int q) { return q == 2 ? -1 : (q == 3 ? 2 : q); }
+
+template <int SUM, int M>
+struct Totals {
+    float S[4][M];
+    float *comp;  // SUM_KAHAN: this wave's [3][M][64] compensation terms in LDS
+    int lane;
+
+    __device__ __forceinline__ void init(float *lds_comp, int ln)
+    {
+        comp = lds_comp;
+        lane = ln;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                S[q][m] = 0.0f;
+                if constexpr (SUM == SUM_KAHAN)
+                    if (comp_slot(q) >= 0) comp[(comp_slot(q) * M + m) * kWave + lane] = 0.0f;
+            }
+    }
+
+    __device__ __forceinline__ void fold(float (&p)[4][M])
+    {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                if (SUM == SUM_KAHAN && comp_slot(q) >= 0) {
+                    float &c = comp[(comp_slot(q) * M + m) * kWave + lane];
+                    const float y = p[q][m] - c;
+                    const float t = S[q][m] + y;
+                    c = (t - S[q][m]) - y;
+                    S[q][m] = t;
+                } else {
+                    S[q][m] += p[q][m];
+                }
+                p[q][m] = 0.0f;
+            }
+    }
+
+    // total of accumulator (q, m) in FP64
+    __device__ __forceinline__ double value(int q, int m) const
+    {
+        if (SUM == SUM_KAHAN && comp_slot(q) >= 0)
+            return (double)S[q][m] - (double)comp[(comp_slot(q) * M + m) * kWave + lane];
+        return (double)S[q][m];
+    }
+};
+
+template <int SUM, int M>
+struct CompLds {
+    static constexpr int kFloats = (SUM == SUM_KAHAN) ? kMaxWaves * 3 * M * kWave : 1;
+};
+
+// Processes samples [jb, je) for the 64*M frequencies starting at k0 (this
+// lane: k0 + lane + 64 m) and leaves the totals in Tot.
+template <int PHASE, int TRIG, int M, int U, int SUM>
+__device__ __forceinline__ void wave_sums(Tile<PHASE> &T, const Records &rec, int64_t jb, int64_t je,
+                                          double f_min, double df, int64_t k0, int lane,
+                                          Totals<SUM, M> &Tot)
 {
+    Freq<PHASE, TRIG, M> F;
+    F.init(f_min, df, k0 + lane);
+    float p[4][M];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            float y = p[q][m] - C[q][m];
-            float t = S[q][m] + y;
-            C[q][m] = (t - S[q][m]) - y;
-            S[q][m] = t;
-            p[q][m] = 0.0f;
+        for (int m = 0; m < M; ++m) p[q][m] = 0.0f;
+    Staged nx;
+    fetch<PHASE>(rec, jb + lane, jb + lane < je, nx);
+    int since_fold = 0;
+    // whole tiles only: the ragged end is padded with neutral samples (see fetch)
+    for (int64_t j0 = jb; j0 < je; j0 += kTile) {
+        stage<PHASE>(T, lane, nx);
+        __builtin_amdgcn_wave_barrier();
+        const int64_t jn = j0 + kTile + lane;
+        fetch<PHASE>(rec, jn, jn < je, nx);  // prefetch the next tile
+#pragma unroll 1
+        for (int j = 0; j < kTile; j += U) {
+            Smp s[U];
+            read_smp<PHASE, U>(T, j, s);
+#pragma unroll
+            for (int u = 0; u < U; ++u) sample_terms<PHASE, TRIG, M>(p, F, s[u]);
         }
+        __builtin_amdgcn_wave_barrier();
+        if (++since_fold == kFoldTiles) {
+            Tot.fold(p);
+            since_fold = 0;
+        }
+    }
+    Tot.fold(p);
 }
 
 // Eqs. (5)-(7) in FP64 from the four sums of Eq. (8) (SS = Nt - CC).
@@ -404,64 +512,11 @@ __device__ __forceinline__ float pn_from_sums(double XC, double XS, double CC, d
     return (float)(P * inv_var);
 }
 
-// Processes samples [jb, je) for the 64*M frequencies starting at k0 (this
-// lane: k0 + lane + 64 m).  Leaves compensated totals in S, C.
-template <int PHASE, int TRIG, int M>
-__device__ __forceinline__ void wave_sums(Tile<PHASE> &T, const Records &rec, int64_t jb, int64_t je,
-                                          double f_min, double df, int64_t k0, int lane,
-                                          float (&S)[4][M], float (&C)[4][M])
-{
-    Freq<PHASE, TRIG, M> F;
-    F.init(f_min, df, k0 + lane);
-    float p[4][M];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            p[q][m] = 0.0f;
-            S[q][m] = 0.0f;
-            C[q][m] = 0.0f;
-        }
-    Staged nx;
-    nx.th = nx.tl = nx.x = nx.rs = 0.0f;
-    nx.rc = 1.0f;
-    fetch<PHASE>(rec, jb + lane, jb + lane < je, nx);
-    int since_fold = 0;
-    for (int64_t j0 = jb; j0 < je; j0 += kTile) {
-        stage<PHASE>(T, lane, nx);
-        __builtin_amdgcn_wave_barrier();
-        const int64_t jn = j0 + kTile + lane;
-        fetch<PHASE>(rec, jn, jn < je, nx);  // prefetch the next tile
-        const int64_t rem = je - j0;
-        if (rem >= kTile) {
-#pragma unroll 1
-            for (int j = 0; j < kTile; j += 4) {
-                Smp s[4];
-                read_smp4<PHASE>(T, j, s);
-#pragma unroll
-                for (int u = 0; u < 4; ++u) sample_terms<PHASE, TRIG, M>(p, F, s[u]);
-            }
-        } else {
-            const int n = (int)rem;
-#pragma unroll 1
-            for (int j = 0; j < n; ++j) {
-                Smp s = read_smp<PHASE>(T, j);
-                sample_terms<PHASE, TRIG, M>(p, F, s);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (++since_fold == kFoldTiles) {
-            fold<M>(p, S, C);
-            since_fold = 0;
-        }
-    }
-    fold<M>(p, S, C);
-}
-
-template <int PHASE, int TRIG, int M>
+template <int PHASE, int TRIG, int M, int U, int SUM>
 __global__ void __launch_bounds__(256) pgram_kernel(PgramArgs a)
 {
     __shared__ Tile<PHASE> tiles[kMaxWaves];
+    __shared__ float comp_lds[CompLds<SUM, M>::kFloats];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);  // wave-uniform
     const int nw = blockDim.x / kWave;
@@ -472,36 +527,30 @@ __global__ void __launch_bounds__(256) pgram_kernel(PgramArgs a)
     const int64_t jb = (int64_t)split * a.chunk;
     const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
 
-    float S[4][M], C[4][M];
-    wave_sums<PHASE, TRIG, M>(tiles[wave], a.rec, jb, je, a.f_min, a.df, k0, lane, S, C);
+    Totals<SUM, M> Tot;
+    Tot.init(comp_lds + (SUM == SUM_KAHAN ? wave * 3 * M * kWave : 0), lane);
+    wave_sums<PHASE, TRIG, M, U, SUM>(tiles[wave], a.rec, jb, je, a.f_min, a.df, k0, lane, Tot);
 
-    if (a.splits == 1) {
-        const double Nt = (double)a.Nt;
-        const double inv_var = a.stats->inv_var;
+    // The chunk's four sums leave as FP32 (one rounding of the compensated
+    // total); the FP64 merge and the epilogue run in pgram_reduce_kernel, so the
+    // epilogue's FP64 constants never occupy registers during the sample loop.
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int64_t k = k0 + lane + (int64_t)kWave * m;
-            if (k < a.Nf) {
-                double v[4];
+    for (int m = 0; m < M; ++m) {
+        const int64_t k = k0 + lane + (int64_t)kWave * m;
+        if (k < a.Nf) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (double)S[q][m] - (double)C[q][m];
-                a.Pn[k] = pn_from_sums(v[0], v[1], v[2], v[3], Nt, inv_var);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const int64_t k = k0 + lane + (int64_t)kWave * m;
-            if (k < a.Nf) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    a.part[((int64_t)split * 4 + q) * a.Nf + k] = (double)S[q][m] - (double)C[q][m];
-            }
+            for (int q = 0; q < 4; ++q) a.part[((int64_t)split * 4 + q) * a.Nf + k] = (float)Tot.value(q, m);
         }
     }
 }
 
-__global__ void __launch_bounds__(256) pgram_reduce_kernel(const double *__restrict__ part, int splits,
+// number of neutral samples that pad [0, Nt) to whole tiles
+__host__ __device__ __forceinline__ int64_t pad_count(int64_t Nt)
+{
+    return (Nt + kTile - 1) / kTile * kTile - Nt;
+}
+
+__global__ void __launch_bounds__(256) pgram_reduce_kernel(const float *__restrict__ part, int splits,
                                                            int64_t Nf, int64_t Nt,
                                                            const CurveStats *__restrict__ st,
                                                            float *__restrict__ Pn)
@@ -511,7 +560,8 @@ __global__ void __launch_bounds__(256) pgram_reduce_kernel(const double *__restr
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     for (int s = 0; s < splits; ++s)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += part[((int64_t)s * 4 + q) * Nf + k];
+        for (int q = 0; q < 4; ++q) v[q] += (double)part[((int64_t)s * 4 + q) * Nf + k];
+    v[2] -= (double)pad_count(Nt);  // chunks are whole tiles except the last
     Pn[k] = pn_from_sums(v[0], v[1], v[2], v[3], (double)Nt, st->inv_var);
 }
 
@@ -521,27 +571,40 @@ __global__ void __launch_bounds__(256) pgram_reduce_kernel(const double *__restr
 typedef void (*PgramFn)(PgramArgs);
 
 struct Variant {
-    int phase, trig, m;
+    int phase, trig, m, unroll, sum;
     PgramFn fn;
     const char *name;
 };
 
-#define LSP_VARIANT(P, T, M) {P, T, M, pgram_kernel<P, T, M>, "pgram_kernel<" #P "," #T "," #M ">"}
+#define LSP_V(P, T, M, U, S) \
+    {P, T, M, U, S, pgram_kernel<P, T, M, U, S>, "pgram_kernel<" #P "," #T "," #M "," #U "," #S ">"}
 
 static const Variant kVariants[] = {
-    LSP_VARIANT(PH_SPLIT, TR_RECUR, 4),    LSP_VARIANT(PH_SPLIT, TR_RECUR, 8),
-    LSP_VARIANT(PH_SPLIT, TR_RECUR, 12),   LSP_VARIANT(PH_SPLIT, TR_RECUR, 16),
-    LSP_VARIANT(PH_SPLIT, TR_DIRECT, 1),   LSP_VARIANT(PH_SPLIT, TR_DIRECT, 2),
-    LSP_VARIANT(PH_SPLIT, TR_DIRECT, 4),   LSP_VARIANT(PH_SPLIT32, TR_RECUR, 8),
-    LSP_VARIANT(PH_SPLIT32, TR_RECUR, 16), LSP_VARIANT(PH_SPLIT32, TR_DIRECT, 1),
-    LSP_VARIANT(PH_SPLIT32, TR_DIRECT, 4), LSP_VARIANT(PH_NAIVE, TR_DIRECT, 1),
-    LSP_VARIANT(PH_NAIVE, TR_DIRECT, 2),   LSP_VARIANT(PH_NAIVE, TR_DIRECT, 4),
+    // split phase, frequency recurrence, compensated sums
+    LSP_V(PH_SPLIT, TR_RECUR, 4, 4, SUM_KAHAN),   LSP_V(PH_SPLIT, TR_RECUR, 8, 4, SUM_KAHAN),
+    LSP_V(PH_SPLIT, TR_RECUR, 8, 2, SUM_KAHAN),   LSP_V(PH_SPLIT, TR_RECUR, 12, 2, SUM_KAHAN),
+    LSP_V(PH_SPLIT, TR_RECUR, 12, 4, SUM_KAHAN),  LSP_V(PH_SPLIT, TR_RECUR, 14, 2, SUM_KAHAN),
+    LSP_V(PH_SPLIT, TR_RECUR, 16, 2, SUM_KAHAN),  LSP_V(PH_SPLIT, TR_RECUR, 16, 1, SUM_KAHAN),
+    // split phase, frequency recurrence, two-level sums
+    LSP_V(PH_SPLIT, TR_RECUR, 8, 4, SUM_TWO),     LSP_V(PH_SPLIT, TR_RECUR, 12, 2, SUM_TWO),
+    LSP_V(PH_SPLIT, TR_RECUR, 14, 2, SUM_TWO),    LSP_V(PH_SPLIT, TR_RECUR, 16, 2, SUM_TWO),
+    LSP_V(PH_SPLIT, TR_RECUR, 20, 2, SUM_TWO),    LSP_V(PH_SPLIT, TR_RECUR, 24, 2, SUM_TWO),
+    // split phase, direct trigonometry
+    LSP_V(PH_SPLIT, TR_DIRECT, 1, 4, SUM_KAHAN),  LSP_V(PH_SPLIT, TR_DIRECT, 2, 4, SUM_KAHAN),
+    LSP_V(PH_SPLIT, TR_DIRECT, 4, 4, SUM_KAHAN),
+    // all-FP32 split phase
+    LSP_V(PH_SPLIT32, TR_RECUR, 8, 4, SUM_KAHAN), LSP_V(PH_SPLIT32, TR_RECUR, 16, 2, SUM_KAHAN),
+    LSP_V(PH_SPLIT32, TR_DIRECT, 1, 4, SUM_KAHAN), LSP_V(PH_SPLIT32, TR_DIRECT, 4, 4, SUM_KAHAN),
+    // the paper's FP32 arithmetic (two-level sums, as its chunked totals)
+    LSP_V(PH_NAIVE, TR_DIRECT, 1, 4, SUM_TWO),    LSP_V(PH_NAIVE, TR_DIRECT, 2, 4, SUM_TWO),
+    LSP_V(PH_NAIVE, TR_DIRECT, 4, 4, SUM_TWO),
 };
 
-static const Variant *find_variant(int phase, const lsp_tile &tile)
+static const Variant *find_variant(int phase, const lsp_tile &t)
 {
     for (const Variant &v : kVariants)
-        if (v.phase == phase && v.trig == tile.trig && v.m == tile.m) return &v;
+        if (v.phase == phase && v.trig == t.trig && v.m == t.m && v.unroll == t.unroll && v.sum == t.sum)
+            return &v;
     return nullptr;
 }
 
@@ -558,6 +621,45 @@ const char *pgram_kernel_name(int phase, const lsp_tile &tile)
     return v ? v->name : "";
 }
 
+// fills unset (zero) unroll/sum fields with the first built variant that matches the rest
+void pgram_complete_tile(int phase, lsp_tile &t)
+{
+    for (const Variant &v : kVariants)
+        if (v.phase == phase && v.trig == t.trig && v.m == t.m && (t.unroll == 0 || v.unroll == t.unroll) &&
+            (t.sum == 0 || v.sum == t.sum)) {
+            t.unroll = v.unroll;
+            t.sum = v.sum;
+            return;
+        }
+}
+
+int pgram_list_tiles(int phase, lsp_tile *out, int cap)
+{
+    int n = 0;
+    for (const Variant &v : kVariants)
+        if (v.phase == phase) {
+            if (out && n < cap) {
+                lsp_tile t;
+                t.trig = v.trig;
+                t.m = v.m;
+                t.waves = 0;
+                t.splits = 0;
+                t.unroll = v.unroll;
+                t.sum = v.sum;
+                out[n] = t;
+            }
+            ++n;
+        }
+    return n;
+}
+
+hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu)
+{
+    const Variant *v = find_variant(phase, tile);
+    if (!v) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, v->fn, kWave * tile.waves, 0);
+}
+
 hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hipStream_t s,
                         hipEvent_t ev0, hipEvent_t ev1)
 {
@@ -572,13 +674,10 @@ hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hip
     if (ev1) hipEventRecord(ev1, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (tile.splits > 1) {
-        const int64_t nb = (a.Nf + 255) / 256;
-        hipLaunchKernelGGL(pgram_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s,
-                           (const double *)a.part, tile.splits, a.Nf, a.Nt, a.stats, a.Pn);
-        e = hipGetLastError();
-    }
-    return e;
+    const int64_t nb = (a.Nf + 255) / 256;
+    hipLaunchKernelGGL(pgram_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const float *)a.part,
+                       tile.splits, a.Nf, a.Nt, a.stats, a.Pn);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -645,6 +744,7 @@ template <int M>
 __global__ void __launch_bounds__(256) batch_pgram_kernel(BatchArgs a)
 {
     __shared__ Tile<PH_SPLIT> tiles[kMaxWaves];
+    __shared__ float comp_lds[CompLds<SUM_KAHAN, M>::kFloats];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     // A wave never takes more than n_items items, so the bound below is a
@@ -668,18 +768,19 @@ __global__ void __launch_bounds__(256) batch_pgram_kernel(BatchArgs a)
         r.xv += cv.off;
         r.rc += cv.off;
         r.rs += cv.off;
-        float S[4][M], C[4][M];
-        wave_sums<PH_SPLIT, TR_RECUR, M>(tiles[wave], r, 0, cv.Nt, cv.f_min, cv.df, k0, lane, S, C);
+        Totals<SUM_KAHAN, M> Tot;
+        Tot.init(comp_lds + wave * 3 * M * kWave, lane);
+        wave_sums<PH_SPLIT, TR_RECUR, M, 4, SUM_KAHAN>(tiles[wave], r, 0, cv.Nt, cv.f_min, cv.df, k0, lane,
+                                                       Tot);
         const double inv_var = a.stats[item.curve].inv_var;
         unsigned long long best = 0ull;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int64_t k = k0 + lane + (int64_t)kWave * m;
             if (k < cv.Nf) {
-                double v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = (double)S[q][m] - (double)C[q][m];
-                const float P = pn_from_sums(v[0], v[1], v[2], v[3], (double)cv.Nt, inv_var);
+                const float P = pn_from_sums(Tot.value(0, m), Tot.value(1, m),
+                                             Tot.value(2, m) - (double)pad_count(cv.Nt), Tot.value(3, m),
+                                             (double)cv.Nt, inv_var);
                 if (a.Pn) a.Pn[cv.pn_off + k] = P;
                 const unsigned long long key =
                     ((unsigned long long)__float_as_uint(P) << 32) | (unsigned long long)(0xffffffffu - (unsigned)k);

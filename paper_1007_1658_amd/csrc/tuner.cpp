@@ -4,7 +4,7 @@
 // footnote on the block size).  Here the candidates are every built
 // (trig mode, frequencies per lane) of the requested phase mode, crossed
 // with waves per workgroup and sample-axis splits around the occupancy
-// heuristic.  Each candidate is timed with HIP events on synthetic data of
+// heuristic (for the split phases only the compensated-sum variants).  Each candidate is timed with HIP events on synthetic data of
 // the requested size; the fastest is kept per (arch, CU count, phase,
 // power-of-two bucket of Nt and of Nf), in memory and optionally in a JSON
 // file.
@@ -112,25 +112,30 @@ lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream, lsp
 
     std::vector<lsp_tile> cand;
     if (result == LSP_OK) {
-        const int trigs[2] = {LSP_TRIG_RECUR, LSP_TRIG_DIRECT};
-        const int ms[7] = {1, 2, 4, 8, 12, 16, 0};
-        for (int tr : trigs)
-            for (int i = 0; ms[i]; ++i)
-                for (int w : {2, 4}) {
-                    lsp_tile t;
-                    t.trig = tr;
-                    t.m = ms[i];
-                    t.waves = w;
-                    const int h = heuristic_splits(Nt, Nf, t.m, cus);
-                    for (int sp : {std::max(1, h / 2), h, h * 2}) {
-                        t.splits = sp;
-                        if (!pgram_tile_supported(phase, t)) continue;
-                        bool dup = false;
-                        for (auto &c : cand)
-                            dup |= (c.trig == t.trig && c.m == t.m && c.waves == t.waves && c.splits == t.splits);
-                        if (!dup) cand.push_back(t);
-                    }
+        const int nv = pgram_list_tiles(phase, nullptr, 0);
+        std::vector<lsp_tile> built((size_t)nv);
+        pgram_list_tiles(phase, built.data(), nv);
+        // the split phases keep their compensated sums: two-level variants are
+        // reachable by explicit request only
+        const int want_sum = (phase == LSP_PHASE_NAIVE) ? LSP_SUM_TWO : LSP_SUM_KAHAN;
+        for (lsp_tile t : built)
+            for (int w : {2, 4}) {
+                if (t.sum != want_sum) continue;
+                t.waves = w;
+                int per_cu = 0;
+                t.splits = 1;
+                if (pgram_occupancy(phase, t, &per_cu) != hipSuccess) per_cu = 0;
+                const int h = heuristic_splits(Nt, Nf, t.m, cus, w, per_cu);
+                for (int sp : {h, std::max(1, (h * 3) / 4), (h * 3 + 1) / 2}) {
+                    t.splits = sp;
+                    if (!pgram_tile_supported(phase, t)) continue;
+                    bool dup = false;
+                    for (auto &c : cand)
+                        dup |= (c.trig == t.trig && c.m == t.m && c.waves == t.waves && c.splits == t.splits &&
+                                c.unroll == t.unroll && c.sum == t.sum);
+                    if (!dup) cand.push_back(t);
                 }
+            }
     }
     lsp_tile win;
     std::memset(&win, 0, sizeof(win));
@@ -182,6 +187,20 @@ lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream, lsp
     return LSP_OK;
 }
 
+int32_t lsp_list_tiles(int32_t phase, lsp_tile *out, int32_t cap)
+{
+    if (phase != LSP_PHASE_SPLIT && phase != LSP_PHASE_NAIVE && phase != LSP_PHASE_SPLIT32) return -1;
+    return pgram_list_tiles(phase, out, cap < 0 ? 0 : cap);
+}
+
+lsp_status lsp_tune_lookup(int64_t Nt, int64_t Nf, int32_t phase, lsp_tile *tile)
+{
+    if (!tile || Nt < 1 || Nf < 1) return LSP_ERR_INVALID_ARG;
+    const int cus = device_cus();
+    if (cus <= 0) return LSP_ERR_NO_DEVICE;
+    return tuner_lookup(device_arch(), cus, phase, Nt, Nf, tile) ? LSP_OK : LSP_ERR_INVALID_ARG;
+}
+
 lsp_status lsp_tune_cache_save(const char *path)
 {
     if (!path) path = default_path();
@@ -189,13 +208,13 @@ lsp_status lsp_tune_cache_save(const char *path)
     std::lock_guard<std::mutex> lock(g_mu);
     std::ofstream f(path);
     if (!f) return LSP_ERR_INVALID_ARG;
-    f << "{\n  \"format\": \"mi355lsp-tune-1\",\n  \"entries\": [";
+    f << "{\n  \"format\": \"mi355lsp-tune-2\",\n  \"entries\": [";
     bool first = true;
     for (auto &kv : g_cache) {
         const lsp_tile &t = kv.second.tile;
         f << (first ? "\n" : ",\n") << "    {\"key\": \"" << kv.first << "\", \"trig\": " << t.trig
           << ", \"m\": " << t.m << ", \"waves\": " << t.waves << ", \"splits\": " << t.splits
-          << ", \"ms\": " << kv.second.ms << "}";
+          << ", \"unroll\": " << t.unroll << ", \"sum\": " << t.sum << ", \"ms\": " << kv.second.ms << "}";
         first = false;
     }
     f << "\n  ]\n}\n";
@@ -212,7 +231,7 @@ lsp_status lsp_tune_cache_load(const char *path)
     std::stringstream ss;
     ss << f.rdbuf();
     const std::string s = ss.str();
-    if (s.find("mi355lsp-tune-1") == std::string::npos) return LSP_ERR_INVALID_ARG;
+    if (s.find("mi355lsp-tune-2") == std::string::npos) return LSP_ERR_INVALID_ARG;
     auto num = [&](size_t from, size_t to, const char *field, double *v) {
         const std::string pat = std::string("\"") + field + "\":";
         size_t p = s.find(pat, from);
@@ -227,15 +246,18 @@ lsp_status lsp_tune_cache_load(const char *path)
         const size_t ke = s.find('"', kb);
         const size_t end = s.find('}', kb);
         if (ke == std::string::npos || end == std::string::npos) return LSP_ERR_INVALID_ARG;
-        double tr, m, w, sp, ms;
+        double tr, m, w, sp, un, su, ms;
         if (!num(ke, end, "trig", &tr) || !num(ke, end, "m", &m) || !num(ke, end, "waves", &w) ||
-            !num(ke, end, "splits", &sp) || !num(ke, end, "ms", &ms))
+            !num(ke, end, "splits", &sp) || !num(ke, end, "unroll", &un) || !num(ke, end, "sum", &su) ||
+            !num(ke, end, "ms", &ms))
             return LSP_ERR_INVALID_ARG;
         Entry e;
         e.tile.trig = (int32_t)tr;
         e.tile.m = (int32_t)m;
         e.tile.waves = (int32_t)w;
         e.tile.splits = (int32_t)sp;
+        e.tile.unroll = (int32_t)un;
+        e.tile.sum = (int32_t)su;
         e.ms = ms;
         loaded[s.substr(kb, ke - kb)] = e;
         pos = end;

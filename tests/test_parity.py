@@ -18,12 +18,12 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 import paper_1007_1658_amd as lsp  # noqa: E402
 
+TRIG_NAME = {lsp.LSP_TRIG_DIRECT: "direct", lsp.LSP_TRIG_RECUR: "recur"}
+SUM_NAME = {lsp.LSP_SUM_KAHAN: "kahan", lsp.LSP_SUM_TWO: "two"}
+
 # every launch shape built into the library, per phase mode
-SPLIT_SHAPES = [("recur", m) for m in (4, 8, 12, 16)] + [("direct", m) for m in (1, 2, 4)]
-SPLIT32_SHAPES = [("recur", 8), ("recur", 16), ("direct", 1), ("direct", 4)]
-NAIVE_SHAPES = [("direct", 1), ("direct", 2), ("direct", 4)]
-ALL = ([("split",) + s for s in SPLIT_SHAPES] + [("split32",) + s for s in SPLIT32_SHAPES]
-       + [("naive",) + s for s in NAIVE_SHAPES])
+ALL = [(ph, TRIG_NAME[t["trig"]], t["m"], t["unroll"], SUM_NAME[t["sum"]])
+       for ph in ("split", "split32", "naive") for t in lsp.lsp_list_tiles(ph)]
 
 
 @pytest.fixture(scope="module")
@@ -33,14 +33,15 @@ def c0_case():
     return c, P
 
 
-@pytest.mark.parametrize("phase,trig,m", ALL)
+@pytest.mark.parametrize("phase,trig,m,unroll,summ", ALL)
 @pytest.mark.parametrize("waves,splits", [(4, 1), (2, 3)])
-def test_c0_all_shapes(c0_case, phase, trig, m, waves, splits):
+def test_c0_all_shapes(c0_case, phase, trig, m, unroll, summ, waves, splits):
     c, P = c0_case
-    print(f"c0 phase={phase} trig={trig} m={m} waves={waves} splits={splits}", flush=True)
+    print(f"c0 phase={phase} trig={trig} m={m} unroll={unroll} sum={summ} waves={waves} splits={splits}",
+          flush=True)
     t, x = to_dev(c)
-    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, phase=phase, trig=trig, m=m,
-                                waves=waves, splits=splits).cpu().numpy()
+    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, phase=phase, trig=trig, m=m, unroll=unroll,
+                                sum=summ, waves=waves, splits=splits).cpu().numpy()
     assert rel_err(Pg, P) <= REL_TOL
     assert peak_matches(Pg, P)
 
@@ -49,7 +50,7 @@ def test_c0_all_shapes(c0_case, phase, trig, m, waves, splits):
     (2, 1, 1), (3, 7, 1), (63, 100, 1), (64, 64, 1), (65, 513, 2), (130, 1025, 3),
     (1000, 511, 4), (4097, 3000, 5), (257, 8193, 1), (5000, 20, 64),
 ])
-@pytest.mark.parametrize("phase,trig,m", [("split", "recur", 8), ("split", "recur", 16),
+@pytest.mark.parametrize("phase,trig,m", [("split", "recur", 8), ("split", "recur", 16), ("split", "recur", 14),
                                           ("split", "direct", 1), ("split32", "recur", 8),
                                           ("naive", "direct", 4)])
 def test_ragged_sizes(Nt, Nf, splits, phase, trig, m):
@@ -178,7 +179,7 @@ def test_autotune_and_cache_roundtrip(tmp_path):
     f = tmp_path / "tune.json"
     lsp.lsp_tune_cache_save(str(f))
     lsp.lsp_tune_cache_load(str(f))
-    assert "mi355lsp-tune-1" in f.read_text()
+    assert "mi355lsp-tune-2" in f.read_text()
 
 
 def test_invalid_arguments_raise():
