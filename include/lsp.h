@@ -161,6 +161,39 @@ lsp_status lsp_periodogram_batched(const double *t, const float *x,
                                    int64_t *kbest, double *fbest,
                                    uint64_t *t_ns, void *stream);
 
+/* ---- Monte-Carlo noise periodograms (Section 6.2: simulations of the
+   periodogram's statistics are the other use the paper names) ----------------
+
+   For each sampling pattern p (times t[off[p]..off[p+1]), own grid
+   f_min[p] + k df[p], k < Nf[p]) and each realization r < R, draws white
+   Gaussian values x_j ~ N(0, 1) on the device and returns the maximum of the
+   normalized periodogram: pmax[p * R + r].  Deviate j of realization (p, r)
+   comes from the Philox4x32-10 counter generator (Salmon et al., SC'11) with
+   key `seed` and counter (j, stream_base + p R + r), turned into a normal by
+   Box-Muller on 24-bit uniforms; so results do not depend on how calls are
+   batched.  t: device FP64; off, f_min, df, Nf: host arrays of the pattern
+   shape; pmax: device FP32 [n_pat R].  Asynchronous.  LSP_ERR_INVALID_ARG as
+   for lsp_periodogram_batched, or when n_pat R >= 2^31. */
+lsp_status lsp_mc_maxpower(const double *t, const int64_t *off, int32_t n_pat,
+                           const double *f_min, const double *df, const int64_t *Nf,
+                           int32_t R, uint64_t seed, uint64_t stream_base, float *pmax,
+                           void *stream);
+
+/* Spectral-window features of each sampling pattern (inputs of the false-alarm
+   surrogate).  W(f_k) = |sum_j exp(2 pi i f_k t_j)|^2 on the pattern's grid;
+   feat[p*68 + b], b < 64: log10 of mean(W)/Nt over the 64 bands of the
+   frequency index k in [round(Nf^(b/64)) - 1, round(Nf^((b+1)/64)) - 1),
+   outer edges 0 and Nf (at least one k each); feat[p*68 + 64..67]: log10 Nt, log10 T, gap fraction
+   (the spacings longer than five mean spacings, summed, over T; times must be
+   sorted), log10 Nf.  feat: device FP32 [n_pat][68].  Asynchronous. */
+lsp_status lsp_window_features(const double *t, const int64_t *off, int32_t n_pat,
+                               const double *f_min, const double *df, const int64_t *Nf,
+                               float *feat, void *stream);
+
+/* The first n normal deviates of counter stream `stream_id` under key `seed`,
+   exactly as lsp_mc_maxpower draws them (out: device FP32 [n]). */
+lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out, void *stream);
+
 /* ---- autotuner -----------------------------------------------------------------
 
    Times the built launch shapes of the single-curve kernel on synthetic data

@@ -39,6 +39,10 @@ def _lib():
         lib.oracle_window.restype = i32
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = i32
+        lib.oracle_philox4x32_10.argtypes = [P, P, P]
+        lib.oracle_philox4x32_10.restype = None
+        lib.oracle_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint64, i64, P]
+        lib.oracle_normals.restype = None
         _LIB = lib
     return _LIB
 
@@ -138,3 +142,59 @@ def batched_peaks(t, x, off, f_min, df, Nf, curves=None, threads=0):
         P = periodogram(t[a:b], x[a:b], float(f_min[c]), float(df[c]), Nf=int(Nf[c]), threads=threads)
         res[int(c)] = peak(P)
     return res
+
+
+# ---- Monte Carlo and surrogate inputs -----------------------------------------------
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: four 32-bit counter words, two key words."""
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    out = np.empty(4, dtype=np.uint32)
+    _lib().oracle_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normals(seed, stream, n):
+    """The first n N(0,1) deviates of counter stream `stream` (FP64)."""
+    out = np.empty(int(n), dtype=np.float64)
+    _lib().oracle_normals(int(seed) & (2**64 - 1), int(stream) & (2**64 - 1), int(n), _ptr(out))
+    return out
+
+
+def mc_maxpower(t, f_min, df, Nf, R, seed, stream_base=0, threads=0):
+    """max Pn of R white-noise realizations (draws as the GPU's), one pattern."""
+    res = np.empty(int(R))
+    for r in range(int(R)):
+        x = normals(seed, stream_base + r, len(t))
+        res[r] = periodogram(t, x, f_min, df, Nf=Nf, threads=threads).max()
+    return res
+
+
+N_BANDS = 64
+
+
+def band_limits(Nf):
+    """[lo, hi) frequency-index ranges of the 64 log-spaced window bands."""
+    Nf = int(Nf)
+    out = []
+    for b in range(N_BANDS):
+        # edges round(Nf^(b/64)) - 1, the outer ones fixed at 0 and Nf
+        lo = 0 if b == 0 else int(np.rint(np.exp(np.log(Nf) * b / N_BANDS))) - 1
+        hi = Nf if b == N_BANDS - 1 else int(np.rint(np.exp(np.log(Nf) * (b + 1) / N_BANDS))) - 1
+        lo = min(max(lo, 0), Nf - 1)
+        hi = min(max(hi, lo + 1), Nf)
+        out.append((lo, hi))
+    return out
+
+
+def window_features(t, f_min, df, Nf, threads=0):
+    """The 68 surrogate inputs of one sorted pattern, from the FP64 window."""
+    t = _f64(t)
+    W = window(t, f_min, df, Nf, threads=threads)
+    Nt = t.size
+    f = [np.log10(W[lo:hi].mean() / Nt + 1e-30) for lo, hi in band_limits(Nf)]
+    T = t.max() - t.min()
+    d = np.diff(t)
+    gap = d[d > 5.0 * T / (Nt - 1)].sum() / T
+    return np.array(f + [np.log10(Nt), np.log10(T), gap, np.log10(Nf)])

@@ -308,3 +308,44 @@ int oracle_window(const double *t, int64_t Nt, double f_min, double df,
 }
 
 int oracle_max_threads(void) { return omp_get_max_threads(); }
+
+/* ---- counter-based normal deviates (white-noise Monte Carlo) -------------
+   Philox4x32-10 as defined by Salmon, Moraes, Dror & Shaw (SC'11): per round,
+   the products of the first and third counter words with the two multipliers
+   are split into high and low halves; the new counter is
+   (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)), and the
+   key is advanced by the two Weyl increments after each of the ten rounds. */
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)b;
+        uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)a;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* Deviate j of stream s under key `seed`: counter (j, s_lo, s_hi, 0); the top
+   24 bits of the first two output words give u1, u2 = (w + 1/2) / 2^24 in
+   (0, 1); Box-Muller z = sqrt(-2 ln u1) cos(2 pi u2), here in FP64. */
+void oracle_normals(uint64_t seed, uint64_t stream, int64_t n, double *out)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t j = 0; j < n; ++j) {
+        const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)stream, (uint32_t)(stream >> 32), 0u};
+        uint32_t w[4];
+        oracle_philox4x32_10(ctr, key, w);
+        const double u1 = ((double)(w[0] >> 8) + 0.5) / 16777216.0;
+        const double u2 = ((double)(w[1] >> 8) + 0.5) / 16777216.0;
+        out[j] = sqrt(-2.0 * log(u1)) * cos(TWO_PI * u2);
+    }
+}

@@ -77,6 +77,9 @@ SIGNATURES = {
     "lsp_periodogram": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P]),
     "lsp_periodogram_ex": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P, ctypes.POINTER(lsp_options)]),
     "lsp_periodogram_batched": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
+    "lsp_mc_maxpower": (_I32, [_P, _P, _I32, _P, _P, _P, _I32, ctypes.c_uint64, ctypes.c_uint64, _P, _P]),
+    "lsp_window_features": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "lsp_normals": (_I32, [ctypes.c_uint64, ctypes.c_uint64, _I64, _P, _P]),
     "lsp_autotune": (_I32, [_I64, _I64, _I32, _P, ctypes.POINTER(lsp_tile), ctypes.POINTER(_D)]),
     "lsp_tune_lookup": (_I32, [_I64, _I64, _I32, ctypes.POINTER(lsp_tile)]),
     "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
@@ -249,6 +252,67 @@ def lsp_periodogram_batched(t, x, off, f_min, df, Nf, want_pn=False, want_times=
             _ptr(out.get("Pn")), _ptr(out["pmax"]), _ptr(out["kbest"]), _ptr(out["fbest"]),
             _ptr(out.get("t_ns")), _stream_ptr(stream))
     _check(st, "lsp_periodogram_batched")
+    return out
+
+
+N_FEATURES = 68
+
+
+def _host_shape(off, f_min, df, Nf):
+    off = np.ascontiguousarray(np.asarray(off, dtype=np.int64))
+    f_min = np.ascontiguousarray(np.asarray(f_min, dtype=np.float64))
+    df = np.ascontiguousarray(np.asarray(df, dtype=np.float64))
+    Nf = np.ascontiguousarray(np.asarray(Nf, dtype=np.int64))
+    n = off.size - 1
+    if n < 1 or f_min.size != n or df.size != n or Nf.size != n:
+        raise ValueError("pattern arrays disagree in length")
+    return off, f_min, df, Nf, n
+
+
+def lsp_mc_maxpower(t, off, f_min, df, Nf, R: int, seed: int, stream_base: int = 0, out=None, stream=None):
+    """max Pn of R white-noise realizations on each pattern: device float32 [n_pat, R]."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    off, f_min, df, Nf, n = _host_shape(off, f_min, df, Nf)
+    if int(off[-1]) != t.numel():
+        raise ValueError("off[-1] must equal the number of samples")
+    if out is None:
+        out = torch.empty((n, int(R)), dtype=torch.float32, device=t.device)
+    _dev_tensor(out, torch.float32, "out")
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    with torch.cuda.device(t.device):
+        st = lib().lsp_mc_maxpower(_ptr(t), hp(off), n, hp(f_min), hp(df), hp(Nf), int(R),
+                                   int(seed) & (2**64 - 1), int(stream_base) & (2**64 - 1), _ptr(out),
+                                   _stream_ptr(stream))
+    _check(st, "lsp_mc_maxpower")
+    return out
+
+
+def lsp_window_features(t, off, f_min, df, Nf, out=None, stream=None):
+    """Spectral-window features of each pattern: device float32 [n_pat, 68]."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    off, f_min, df, Nf, n = _host_shape(off, f_min, df, Nf)
+    if int(off[-1]) != t.numel():
+        raise ValueError("off[-1] must equal the number of samples")
+    if out is None:
+        out = torch.empty((n, N_FEATURES), dtype=torch.float32, device=t.device)
+    _dev_tensor(out, torch.float32, "out")
+    hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    with torch.cuda.device(t.device):
+        st = lib().lsp_window_features(_ptr(t), hp(off), n, hp(f_min), hp(df), hp(Nf), _ptr(out),
+                                       _stream_ptr(stream))
+    _check(st, "lsp_window_features")
+    return out
+
+
+def lsp_normals(seed: int, stream_id: int, n: int, device="cuda", stream=None):
+    """The first n deviates of counter stream stream_id (as drawn by lsp_mc_maxpower)."""
+    torch = _torch()
+    out = torch.empty(int(n), dtype=torch.float32, device=device)
+    st = lib().lsp_normals(int(seed) & (2**64 - 1), int(stream_id) & (2**64 - 1), int(n), _ptr(out),
+                           _stream_ptr(stream))
+    _check(st, "lsp_normals")
     return out
 
 

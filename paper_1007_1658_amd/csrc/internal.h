@@ -60,33 +60,58 @@ struct BatchItem {
     int32_t fblock;
 };
 
+// A sampling pattern: a run of times shared by one or more curves (Monte Carlo
+// realizations share their pattern's times and time records).
+struct BatchGroup {
+    int64_t toff;       // first sample in t and in the time records
+    int64_t Nt;
+    double df;          // grid spacing of its curves (sets the recurrence step)
+};
+
 struct BatchCurve {
-    int64_t off;        // first sample
+    int64_t toff;       // first sample in the time records (= its group's)
+    int64_t xoff;       // first sample in x / the value records
     int64_t Nt;
     int64_t Nf;
     int64_t pn_off;     // first output frequency in the CSR Pn array
     double f_min, df;
+    int32_t group;
+    int32_t pad_;
 };
 
+// where the values of a batch come from
+enum { VAL_INPUT = 0, VAL_NORMAL = 1, VAL_ONES = 2 };
+// what the per-frequency epilogue produces
+enum { EPI_PN = 0, EPI_WINDOW = 1 };
+
 struct BatchArgs {
-    Records rec;              // CSR, same offsets as the input samples
-    CurveStats *stats;        // [n]
-    const BatchCurve *curves; // [n]
-    const BatchItem *items;   // [n_items], longest curves first
-    int32_t n_items;
+    float *th, *tl, *rc, *rs;  // time records, indexed by toff + j
+    float *xv;                 // value records, indexed by xoff + j
+    CurveStats *stats;         // [n_curves]
+    double *t_ref;             // [n_groups]
+    const BatchGroup *groups;  // [n_groups]
+    int32_t n_groups;
     int32_t n_curves;
-    uint32_t *queue;          // [1] next item
-    unsigned long long *key;  // [n] (float bits of max Pn) << 32 | ~k
-    unsigned long long *tbeg; // [n]
-    unsigned long long *tend; // [n]
-    unsigned long long *t0;   // [1] launch start
-    float *Pn;                // nullable
-    float *pmax;
-    int64_t *kbest;           // nullable
-    double *fbest;            // nullable
-    uint64_t *t_ns;           // nullable
-    const double *t;          // raw inputs (prep)
-    const float *x;
+    const BatchCurve *curves;  // [n_curves]
+    const BatchItem *items;    // [n_items], longest curves first
+    int32_t n_items;
+    int32_t val_mode;          // VAL_*
+    int32_t epi_mode;          // EPI_*
+    int32_t pad_;
+    uint64_t seed;             // VAL_NORMAL: Philox key
+    uint64_t curve_base;       // VAL_NORMAL: counter offset of curve 0
+    uint32_t *queue;           // [1] next item
+    unsigned long long *key;   // [n] (float bits of max Pn) << 32 | ~k
+    unsigned long long *tbeg;  // [n]
+    unsigned long long *tend;  // [n]
+    unsigned long long *t0;    // [1] launch start
+    float *Pn;                 // nullable (EPI_WINDOW: the window power, required)
+    float *pmax;               // nullable for EPI_WINDOW
+    int64_t *kbest;            // nullable
+    double *fbest;             // nullable
+    uint64_t *t_ns;            // nullable
+    const double *t;           // raw times, indexed by toff + j
+    const float *x;            // raw values (VAL_INPUT), indexed by xoff + j
 };
 
 // ---- kernel launchers (pgram_kernels.hip) --------------------------------------
@@ -101,10 +126,18 @@ void pgram_complete_tile(int phase, lsp_tile &tile);
 int pgram_list_tiles(int phase, lsp_tile *out, int cap);
 hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu);
 
+// ---- batched launchers (batch_kernels.hip) ---------------------------------------
 hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,
                           hipStream_t s);
 int batched_m();
 hipError_t batched_occupancy(int waves, int *blocks_per_cu);
+// window-power band features of each group (curves = groups, EPI_WINDOW done)
+hipError_t launch_window_features(const BatchArgs &a, float *feat, int n_feat, hipStream_t s);
+// n standard normal deviates of counter stream `curve` (testing the generator)
+hipError_t launch_normals(uint64_t seed, uint64_t curve, int64_t n, float *out, hipStream_t s);
+
+constexpr int kWindowBands = 64;    // log-spaced bands of the spectral-window features
+constexpr int kFeatures = kWindowBands + 4;
 
 // records a message for lsp_last_error() on this host thread (lsp_host.cpp)
 void set_last_error(const char *msg);

@@ -53,6 +53,7 @@ struct BatchGraph {
 struct StreamCtx {
     Buffer ws;        // single-curve workspace
     Buffer bws;       // batched workspace
+    Buffer mws;       // Monte-Carlo / window workspace
     uint64_t plan_key = 0;  // batch plan currently resident in bws
     BatchGraph graph;
 };
@@ -363,11 +364,73 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t n)
     return h;
 }
 
-struct BatchLayout {
-    size_t stats, curves, items, queue, key, tbeg, tend, t0, th, tl, xv, rc, rs, total;
+// Host description of one batched launch.
+struct BatchPlan {
+    std::vector<BatchGroup> groups;
+    std::vector<BatchCurve> curves;
+    std::vector<BatchItem> items;
+    int64_t total_t = 0;   // time samples (sum over groups)
+    int64_t total_x = 0;   // value samples (sum over curves)
+    int64_t total_nf = 0;  // output frequencies (sum over curves)
 };
 
-BatchLayout batch_layout(int64_t n, int64_t n_items, int64_t total_nt)
+// Groups are given by off[] (host, CSR over t); curve c of group g uses the
+// grid of g.  reps curves per group (Monte Carlo), values laid out curve by
+// curve.  Items in longest-processing-time order.
+void build_plan(const int64_t *off, int32_t n_groups, const double *f_min, const double *df, const int64_t *Nf,
+                int32_t reps, BatchPlan &P)
+{
+    const int64_t per_wave = (int64_t)kWave * batched_m();
+    P.groups.resize((size_t)n_groups);
+    P.curves.resize((size_t)n_groups * (size_t)reps);
+    int64_t xoff = 0, pn = 0;
+    for (int32_t g = 0; g < n_groups; ++g) {
+        BatchGroup &G = P.groups[(size_t)g];
+        G.toff = off[g];
+        G.Nt = off[g + 1] - off[g];
+        G.df = df[g];
+        for (int32_t r = 0; r < reps; ++r) {
+            BatchCurve &cv = P.curves[(size_t)g * reps + r];
+            cv.toff = G.toff;
+            cv.xoff = xoff;
+            cv.Nt = G.Nt;
+            cv.Nf = Nf[g];
+            cv.pn_off = pn;
+            cv.f_min = f_min[g];
+            cv.df = df[g];
+            cv.group = g;
+            cv.pad_ = 0;
+            xoff += G.Nt;
+            pn += Nf[g];
+        }
+    }
+    P.total_t = off[n_groups];
+    P.total_x = xoff;
+    P.total_nf = pn;
+    P.items.clear();
+    for (size_t c = 0; c < P.curves.size(); ++c) {
+        const int64_t nfb = (P.curves[c].Nf + per_wave - 1) / per_wave;
+        for (int64_t b = 0; b < nfb; ++b) P.items.push_back(BatchItem{(int32_t)c, (int32_t)b});
+    }
+    // every item of curve c costs ~Nt_c * 64 m terms: longest curves first
+    std::stable_sort(P.items.begin(), P.items.end(), [&](const BatchItem &a, const BatchItem &b) {
+        return P.curves[(size_t)a.curve].Nt > P.curves[(size_t)b.curve].Nt;
+    });
+}
+
+uint64_t plan_hash(const BatchPlan &P)
+{
+    uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, P.groups.data(), sizeof(BatchGroup) * P.groups.size());
+    h = fnv1a(h, P.curves.data(), sizeof(BatchCurve) * P.curves.size());
+    return h;
+}
+
+struct BatchLayout {
+    size_t stats, tref, groups, curves, items, queue, key, tbeg, tend, t0, th, tl, rc, rs, xv, pn, pmax, total;
+};
+
+BatchLayout batch_layout(const BatchPlan &P, bool own_pn, bool own_pmax)
 {
     BatchLayout L;
     size_t o = 0;
@@ -376,21 +439,90 @@ BatchLayout batch_layout(int64_t n, int64_t n_items, int64_t total_nt)
         o = align_up(o + bytes);
         return at;
     };
-    L.stats = take(sizeof(CurveStats) * n);
-    L.curves = take(sizeof(BatchCurve) * n);
-    L.items = take(sizeof(BatchItem) * n_items);
+    const size_t nc = P.curves.size(), ng = P.groups.size();
+    L.stats = take(sizeof(CurveStats) * nc);
+    L.tref = take(sizeof(double) * 3 * ng);
+    L.groups = take(sizeof(BatchGroup) * ng);
+    L.curves = take(sizeof(BatchCurve) * nc);
+    L.items = take(sizeof(BatchItem) * P.items.size());
     L.queue = take(sizeof(uint32_t));
-    L.key = take(8 * n);
-    L.tbeg = take(8 * n);
-    L.tend = take(8 * n);
+    L.key = take(8 * nc);
+    L.tbeg = take(8 * nc);
+    L.tend = take(8 * nc);
     L.t0 = take(8);
-    L.th = take(4 * total_nt);
-    L.tl = take(4 * total_nt);
-    L.xv = take(4 * total_nt);
-    L.rc = take(4 * total_nt);
-    L.rs = take(4 * total_nt);
+    L.th = take(4 * (size_t)P.total_t);
+    L.tl = take(4 * (size_t)P.total_t);
+    L.rc = take(4 * (size_t)P.total_t);
+    L.rs = take(4 * (size_t)P.total_t);
+    L.xv = take(4 * (size_t)P.total_x);
+    L.pn = own_pn ? take(4 * (size_t)P.total_nf) : 0;
+    L.pmax = own_pmax ? take(4 * nc) : 0;
     L.total = o;
     return L;
+}
+
+BatchArgs batch_args(char *b, const BatchLayout &L, const BatchPlan &P)
+{
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.th = (float *)(b + L.th);
+    a.tl = (float *)(b + L.tl);
+    a.rc = (float *)(b + L.rc);
+    a.rs = (float *)(b + L.rs);
+    a.xv = (float *)(b + L.xv);
+    a.stats = (CurveStats *)(b + L.stats);
+    a.t_ref = (double *)(b + L.tref);
+    a.groups = (const BatchGroup *)(b + L.groups);
+    a.n_groups = (int32_t)P.groups.size();
+    a.curves = (const BatchCurve *)(b + L.curves);
+    a.n_curves = (int32_t)P.curves.size();
+    a.items = (const BatchItem *)(b + L.items);
+    a.n_items = (int32_t)P.items.size();
+    a.queue = (uint32_t *)(b + L.queue);
+    a.key = (unsigned long long *)(b + L.key);
+    a.tbeg = (unsigned long long *)(b + L.tbeg);
+    a.tend = (unsigned long long *)(b + L.tend);
+    a.t0 = (unsigned long long *)(b + L.t0);
+    return a;
+}
+
+// copies the plan tables to the workspace (synchronous: the host vectors are temporary)
+lsp_status upload_plan(char *b, const BatchLayout &L, const BatchPlan &P, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(b + L.groups, P.groups.data(), sizeof(BatchGroup) * P.groups.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b + L.curves, P.curves.data(), sizeof(BatchCurve) * P.curves.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !P.items.empty())
+        e = hipMemcpyAsync(b + L.items, P.items.data(), sizeof(BatchItem) * P.items.size(),
+                           hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch plan upload");
+    return LSP_OK;
+}
+
+lsp_status persistent_blocks(const DeviceInfo *di, int waves, int *blocks)
+{
+    int per_cu = 0;
+    hipError_t e = batched_occupancy(waves, &per_cu);
+    if (e != hipSuccess) return hip_fail(e, "occupancy query");
+    *blocks = std::max(1, per_cu) * di->cus;
+    return LSP_OK;
+}
+
+bool valid_groups(const int64_t *off, int32_t n, const double *f_min, const double *df, const int64_t *Nf)
+{
+    if (!off || !f_min || !df || !Nf || n < 1 || off[0] != 0) return false;
+    for (int32_t c = 0; c < n; ++c) {
+        const int64_t nt = off[c + 1] - off[c];
+        if (nt < 2 || nt > kMaxNt || Nf[c] < 1 || Nf[c] > kMaxNf || !finite_nonneg(f_min[c]) ||
+            !finite_pos(df[c]) || !std::isfinite(f_min[c] + (double)(Nf[c] - 1) * df[c])) {
+            g_last_error = "invalid curve " + std::to_string(c);
+            return false;
+        }
+    }
+    return true;
 }
 
 }  // namespace
@@ -404,52 +536,22 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     DeviceInfo *di = nullptr;
     lsp_status st = device_info(&dev, &di);
     if (st != LSP_OK) return st;
-    const int M = batched_m();
-    const int64_t per_wave = (int64_t)kWave * M;
 
-    // plan key: everything that shapes the graph
-    uint64_t key = 1469598103934665603ull;
-    key = fnv1a(key, &n, sizeof(n));
-    key = fnv1a(key, off, sizeof(int64_t) * (size_t)(n + 1));
-    key = fnv1a(key, f_min, sizeof(double) * (size_t)n);
-    key = fnv1a(key, df, sizeof(double) * (size_t)n);
-    key = fnv1a(key, Nf, sizeof(int64_t) * (size_t)n);
+    BatchPlan P;
+    build_plan(off, n, f_min, df, Nf, 1, P);
+    const uint64_t plan_key = plan_hash(P);
     const void *ptrs[] = {t, x, Pn, pmax, kbest, fbest, t_ns};
-    const uint64_t plan_key = key;
-    key = fnv1a(key, ptrs, sizeof(ptrs));
+    const uint64_t key = fnv1a(plan_key, ptrs, sizeof(ptrs));
 
     StreamCtx &sc = stream_ctx(dev, s);
     const bool capturing = stream_capturing(s);
-
     // fast path: same shape and pointers as the cached graph
     if (!capturing && sc.graph.exec && sc.graph.key == key) {
         hipError_t e = hipGraphLaunch(sc.graph.exec, s);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         return LSP_OK;
     }
-
-    std::vector<BatchCurve> curves((size_t)n);
-    std::vector<BatchItem> items;
-    int64_t pn_off = 0;
-    for (int32_t c = 0; c < n; ++c) {
-        BatchCurve &cv = curves[(size_t)c];
-        cv.off = off[c];
-        cv.Nt = off[c + 1] - off[c];
-        cv.Nf = Nf[c];
-        cv.pn_off = pn_off;
-        cv.f_min = f_min[c];
-        cv.df = df[c];
-        pn_off += Nf[c];
-        const int64_t nfb = (Nf[c] + per_wave - 1) / per_wave;
-        for (int64_t b = 0; b < nfb; ++b) items.push_back(BatchItem{c, (int32_t)b});
-    }
-    // longest-processing-time first: every item of curve c costs ~Nt_c * 64 M terms
-    std::stable_sort(items.begin(), items.end(), [&](const BatchItem &a, const BatchItem &b) {
-        return curves[(size_t)a.curve].Nt > curves[(size_t)b.curve].Nt;
-    });
-    const int64_t total_nt = off[n];
-    const BatchLayout L = batch_layout(n, (int64_t)items.size(), total_nt);
-
+    const BatchLayout L = batch_layout(P, false, false);
     if (capturing) {
         // launched into the caller's capture: the plan must already be resident
         if (sc.plan_key != plan_key || sc.bws.size < L.total) {
@@ -459,34 +561,13 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     } else if (sc.plan_key != plan_key || sc.bws.size < L.total) {
         st = ensure(sc.bws, L.total, s);
         if (st != LSP_OK) return st;
-        char *b = (char *)sc.bws.ptr;
-        hipError_t e = hipMemcpyAsync(b + L.curves, curves.data(), sizeof(BatchCurve) * curves.size(),
-                                      hipMemcpyHostToDevice, s);
-        if (e == hipSuccess && !items.empty())
-            e = hipMemcpyAsync(b + L.items, items.data(), sizeof(BatchItem) * items.size(),
-                               hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);  // host vectors die with this call
-        if (e != hipSuccess) return hip_fail(e, "batch plan upload");
+        st = upload_plan((char *)sc.bws.ptr, L, P, s);
+        if (st != LSP_OK) return st;
         sc.plan_key = plan_key;
     }
-
-    char *b = (char *)sc.bws.ptr;
-    BatchArgs a;
-    a.rec.th = (float *)(b + L.th);
-    a.rec.tl = (float *)(b + L.tl);
-    a.rec.xv = (float *)(b + L.xv);
-    a.rec.rc = (float *)(b + L.rc);
-    a.rec.rs = (float *)(b + L.rs);
-    a.stats = (CurveStats *)(b + L.stats);
-    a.curves = (const BatchCurve *)(b + L.curves);
-    a.items = (const BatchItem *)(b + L.items);
-    a.n_items = (int32_t)items.size();
-    a.n_curves = n;
-    a.queue = (uint32_t *)(b + L.queue);
-    a.key = (unsigned long long *)(b + L.key);
-    a.tbeg = (unsigned long long *)(b + L.tbeg);
-    a.tend = (unsigned long long *)(b + L.tend);
-    a.t0 = (unsigned long long *)(b + L.t0);
+    BatchArgs a = batch_args((char *)sc.bws.ptr, L, P);
+    a.val_mode = VAL_INPUT;
+    a.epi_mode = EPI_PN;
     a.Pn = Pn;
     a.pmax = pmax;
     a.kbest = kbest;
@@ -494,15 +575,14 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     a.t_ns = t_ns;
     a.t = t;
     a.x = x;
-
     const int waves = 4;
-    int per_cu = 0;
-    hipError_t e = batched_occupancy(waves, &per_cu);
-    if (e != hipSuccess) return hip_fail(e, "occupancy query");
-    const int blocks = std::max(1, per_cu) * di->cus;
+    int blocks = 0;
+    st = persistent_blocks(di, waves, &blocks);
+    if (st != LSP_OK) return st;
 
+    hipError_t e;
     if (capturing || s == nullptr) {
-        e = launch_batched(a, M, blocks, waves, s);
+        e = launch_batched(a, batched_m(), blocks, waves, s);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
         return LSP_OK;
     }
@@ -514,7 +594,7 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     }
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t el = launch_batched(a, M, blocks, waves, s);
+    hipError_t el = launch_batched(a, batched_m(), blocks, waves, s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (el != hipSuccess) {
@@ -533,6 +613,44 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     sc.graph.exec = ex;
     e = hipGraphLaunch(ex, s);
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return LSP_OK;
+}
+
+// Monte-Carlo max power and window features: direct launches on the stream.
+static lsp_status mc_or_window(const double *t, const int64_t *off, int32_t n, const double *f_min,
+                               const double *df, const int64_t *Nf, int32_t reps, uint64_t seed,
+                               uint64_t curve_base, float *pmax, float *feat, hipStream_t s)
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    lsp_status st = device_info(&dev, &di);
+    if (st != LSP_OK) return st;
+    const bool window = feat != nullptr;
+    BatchPlan P;
+    build_plan(off, n, f_min, df, Nf, window ? 1 : reps, P);
+    const BatchLayout L = batch_layout(P, window, false);
+    StreamCtx &sc = stream_ctx(dev, s);
+    st = ensure(sc.mws, L.total, s);
+    if (st != LSP_OK) return st;
+    st = upload_plan((char *)sc.mws.ptr, L, P, s);
+    if (st != LSP_OK) return st;
+    BatchArgs a = batch_args((char *)sc.mws.ptr, L, P);
+    a.val_mode = window ? VAL_ONES : VAL_NORMAL;
+    a.epi_mode = window ? EPI_WINDOW : EPI_PN;
+    a.seed = seed;
+    a.curve_base = curve_base;
+    a.Pn = window ? (float *)((char *)sc.mws.ptr + L.pn) : nullptr;
+    a.pmax = window ? nullptr : pmax;
+    a.t = t;
+    a.x = nullptr;
+    const int waves = 4;
+    int blocks = 0;
+    st = persistent_blocks(di, waves, &blocks);
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_batched(a, batched_m(), blocks, waves, s);
+    if (e == hipSuccess && window) e = launch_window_features(a, feat, kFeatures, s);
+    if (e != hipSuccess) return hip_fail(e, window ? "window features launch" : "Monte-Carlo launch");
     return LSP_OK;
 }
 
@@ -656,23 +774,50 @@ lsp_status lsp_periodogram_batched(const double *t, const float *x, const int64_
                                    void *stream)
 {
     g_last_error.clear();
-    if (!t || !x || !off || !f_min || !df || !Nf || !pmax || n_curves < 1 || off[0] != 0) {
-        g_last_error = "invalid argument";
+    if (!t || !x || !pmax || !valid_groups(off, n_curves, f_min, df, Nf)) {
+        if (g_last_error.empty()) g_last_error = "invalid argument";
         return LSP_ERR_INVALID_ARG;
     }
-    int64_t total_nf = 0;
-    for (int32_t c = 0; c < n_curves; ++c) {
-        const int64_t nt = off[c + 1] - off[c];
-        if (nt < 2 || nt > kMaxNt || Nf[c] < 1 || Nf[c] > kMaxNf || !finite_nonneg(f_min[c]) ||
-            !finite_pos(df[c]) || !std::isfinite(f_min[c] + (double)(Nf[c] - 1) * df[c])) {
-            g_last_error = "invalid curve " + std::to_string(c);
-            return LSP_ERR_INVALID_ARG;
-        }
-        total_nf += Nf[c];
+    return batched_impl(t, x, off, n_curves, f_min, df, Nf, Pn, pmax, kbest, fbest, t_ns, (hipStream_t)stream);
+}
+
+lsp_status lsp_mc_maxpower(const double *t, const int64_t *off, int32_t n_pat, const double *f_min,
+                           const double *df, const int64_t *Nf, int32_t R, uint64_t seed, uint64_t stream_base,
+                           float *pmax, void *stream)
+{
+    g_last_error.clear();
+    if (!t || !pmax || R < 1 || !valid_groups(off, n_pat, f_min, df, Nf) ||
+        (int64_t)n_pat * (int64_t)R > ((int64_t)1 << 31) - 1) {
+        if (g_last_error.empty()) g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
     }
-    (void)total_nf;
-    return batched_impl(t, x, off, n_curves, f_min, df, Nf, Pn, pmax, kbest, fbest, t_ns,
-                        (hipStream_t)stream);
+    return mc_or_window(t, off, n_pat, f_min, df, Nf, R, seed, stream_base, pmax, nullptr, (hipStream_t)stream);
+}
+
+lsp_status lsp_window_features(const double *t, const int64_t *off, int32_t n_pat, const double *f_min,
+                               const double *df, const int64_t *Nf, float *feat, void *stream)
+{
+    g_last_error.clear();
+    if (!t || !feat || !valid_groups(off, n_pat, f_min, df, Nf)) {
+        if (g_last_error.empty()) g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    return mc_or_window(t, off, n_pat, f_min, df, Nf, 1, 0, 0, nullptr, feat, (hipStream_t)stream);
+}
+
+lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out, void *stream)
+{
+    g_last_error.clear();
+    if (!out || n < 0 || n > ((int64_t)1 << 32)) return LSP_ERR_INVALID_ARG;
+    if (n == 0) return LSP_OK;
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    lsp_status st = device_info(&dev, &di);
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_normals(seed, stream_id, n, out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "normals launch");
+    return LSP_OK;
 }
 
 lsp_status lsp_profile_enable(int32_t on)

@@ -246,3 +246,61 @@ def test_thread_count_does_not_change_result():
     a = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=333, threads=1)
     b = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=333, threads=4)
     assert np.array_equal(a, b)
+
+
+# ---- Monte-Carlo generator and surrogate features ----------------------------------------
+
+def _kat():
+    import os
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")):
+        if line.strip() and not line.startswith("#"):
+            v = [int(w, 16) for w in line.split()]
+            rows.append((v[:4], v[4:6], v[6:10]))
+    return rows
+
+
+def test_philox_known_answers():
+    for ctr, key, out in _kat():
+        assert list(oracle.philox4x32_10(ctr, key)) == out
+
+
+def test_normals_are_standard_normal():
+    z = np.concatenate([oracle.normals(12345, s, 20000) for s in range(3)])
+    assert stats.kstest(z, "norm").pvalue > 1e-3
+    assert abs(z.mean()) < 0.02 and abs(z.std() - 1) < 0.02
+    # streams differ, and a stream is reproducible
+    a, b = oracle.normals(1, 0, 100), oracle.normals(1, 1, 100)
+    assert not np.allclose(a, b)
+    assert np.array_equal(a, oracle.normals(1, 0, 100))
+
+
+def test_window_features_even_sampling_closed_form():
+    N, dt = 400, 0.25
+    t = synth.even(N, dt, 3.0)
+    T = t[-1] - t[0]
+    df = 1.0 / (4 * T)
+    Nf = 2 * N
+    feat = oracle.window_features(t, df, df, Nf)
+    f = df + df * np.arange(Nf)
+    W = np.sin(np.pi * f * N * dt) ** 2 / np.sin(np.pi * f * dt) ** 2   # Dirichlet kernel
+    for b, (lo, hi) in enumerate(oracle.band_limits(Nf)):
+        assert abs(feat[b] - np.log10(W[lo:hi].mean() / N)) < 1e-9
+    assert feat[64] == pytest.approx(np.log10(N)) and feat[65] == pytest.approx(np.log10(T))
+    assert feat[66] == 0.0 and feat[67] == pytest.approx(np.log10(Nf))
+
+
+def test_window_gap_fraction_known_gap():
+    t = np.concatenate([np.arange(0.0, 10.0, 0.1), 30.0 + np.arange(0.0, 10.0, 0.1)])
+    T = t[-1] - t[0]
+    feat = oracle.window_features(t, 0.01, 0.01, 50)
+    # one spacing of 30 - 9.9 = 20.1 d exceeds five mean spacings; the rest are 0.1 d
+    assert feat[66] == pytest.approx(20.1 / T, rel=1e-12)
+
+
+def test_band_limits_cover_and_are_monotone():
+    for Nf in (1, 2, 7, 400, 131072):
+        lim = oracle.band_limits(Nf)
+        assert all(0 <= lo < hi <= Nf for lo, hi in lim)
+        assert all(lim[i][0] <= lim[i + 1][0] for i in range(len(lim) - 1))
+        assert lim[-1][1] == Nf or Nf == 1
