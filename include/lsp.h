@@ -194,6 +194,81 @@ lsp_status lsp_window_features(const double *t, const int64_t *off, int32_t n_pa
    exactly as lsp_mc_maxpower draws them (out: device FP32 [n]). */
 lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out, void *stream);
 
+/* ---- false-alarm surrogate ---------------------------------------------------------
+
+   Eq. (3) treats the Nf frequencies as independent; with oversampling they are
+   not, and the number of independent frequencies has to be simulated (Section
+   6.2).  The surrogate learns, per sampling pattern, nine quantiles
+   (tau = 0.5, 0.75, 0.9, 0.95, 0.975, 0.99, 0.995, 0.998, 0.999) of the
+   maximum periodogram power of white noise, from Monte-Carlo maxima made by
+   lsp_mc_maxpower.  Network: features (68, standardized) -> 256 -> 256 -> 256 -> 9,
+   GELU (tanh form) after the first three layers; products on BF16 matrix
+   cores with FP32 accumulation; quantiles q_0 = mu + sigma r_0,
+   q_i = q_{i-1} + sigma softplus(r_i) (monotone).  A model is an ensemble of
+   `members` independently initialized networks; their spread is the
+   uncertainty.  All model entry points are synchronous with respect to the
+   model (one model = one user at a time; they lock it). */
+typedef struct lsp_model lsp_model;
+
+/* Parameters per member (FP32 master weights): W1[256][68], b1[256],
+   W2[256][256], b2, W3[256][256], b3, W4[9][256], b4[9] in this flat order. */
+int64_t lsp_model_param_count(void);
+/* New model with uniform(+-1/sqrt(fan_in)) weights (0.1x for the last layer),
+   zero biases, seeded per member from `seed`.  members in 1..16. */
+lsp_status lsp_model_create(int32_t members, uint64_t seed, lsp_model **out);
+lsp_status lsp_model_destroy(lsp_model *m);
+/* Feature standardization (host FP32 [68] mean and std > 0), the largest
+   |standardized feature| accepted before the Monte-Carlo fallback, and the
+   quantile scale (mu, sigma > 0). */
+lsp_status lsp_model_set_scalers(lsp_model *m, const float *feat_mean, const float *feat_std,
+                                 float feat_zmax, float q_mu, float q_sigma);
+/* FP32 master parameters of one member, flat order above (host [n], n must
+   equal lsp_model_param_count()). */
+lsp_status lsp_model_get_params(const lsp_model *m, int32_t member, float *host, int64_t n);
+lsp_status lsp_model_set_params(lsp_model *m, int32_t member, const float *host, int64_t n);
+/* Binary model file (little-endian): header, scalers, per member the step
+   count and the weights, plus the Adam moments when with_optimizer != 0.
+   Load reports LSP_ERR_MODEL for a missing, truncated or mismatched file. */
+lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_optimizer);
+lsp_status lsp_model_load(const char *path, lsp_model **out);
+
+/* Quantiles of every member: feat device FP32 [B][68] (raw features),
+   q device FP32 [members][B][9].  Asynchronous on stream. */
+lsp_status lsp_mlp_forward(lsp_model *m, const float *feat, int32_t B, float *q, void *stream);
+/* Forward, pinball loss against R Monte-Carlo maxima per pattern
+   (samples device FP32 [B][R]),
+     L = 1/(9B) sum_b sum_i 1/R sum_r rho_tau_i(y_br - q_bi),  rho_tau(u) = u (tau - [u < 0]),
+   and backward of one member.  grad (device FP32 [param_count], flat order)
+   and loss (device FP32 [1]) may be NULL; the gradient also stays inside the
+   model for lsp_mlp_adam_step.  Asynchronous. */
+lsp_status lsp_mlp_grad(lsp_model *m, int32_t member, const float *feat, const float *samples,
+                        int32_t R, int32_t B, float *grad, float *loss, void *stream);
+/* One Adam step (Kingma & Ba, Algorithm 1, bias-corrected moments) of one
+   member with its last gradient; refreshes the BF16 weight copies. */
+lsp_status lsp_mlp_adam_step(lsp_model *m, int32_t member, float lr, float beta1, float beta2,
+                             float eps, void *stream);
+/* The network's matrix product alone: C[M][N] = sum_k A[M][k] B[N][k];
+   A, B device BF16 row-major (K contiguous), C device FP32; M, N, K
+   multiples of 32.  Asynchronous. */
+lsp_status lsp_mlp_gemm_nt(const void *A, const void *B, float *C, int32_t M, int32_t N, int32_t K,
+                           void *stream);
+
+/* FAP of observed maxima: for each pattern p (as in lsp_mc_maxpower, times
+   sorted, Nt >= 4), fap[p] = P(max Pn of white noise >= p_obs[p]).  The CDF
+   of the maximum is interpolated from each member's quantiles, linearly in
+   the Gumbel variate -ln(-ln tau) (extended along the end segments); fap is
+   the members' mean and fap_sigma their standard deviation.  Patterns with
+   fap_sigma > max_sigma, or with a standardized feature beyond the model's
+   range, are answered by Monte Carlo instead (mc_realizations draws, key
+   `seed`; fap = fraction of maxima >= p_obs, fap_sigma its binomial
+   standard error) and flagged in used_mc (may be NULL).  p_obs, fap,
+   fap_sigma, used_mc: device [n_pat].  Synchronous (the fallback decision
+   reads the spreads back). */
+lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, int32_t n_pat,
+                             const double *f_min, const double *df, const int64_t *Nf,
+                             const float *p_obs, float *fap, float *fap_sigma, int32_t *used_mc,
+                             float max_sigma, int32_t mc_realizations, uint64_t seed, void *stream);
+
 /* ---- autotuner -----------------------------------------------------------------
 
    Times the built launch shapes of the single-curve kernel on synthetic data

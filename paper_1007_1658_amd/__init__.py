@@ -80,6 +80,20 @@ SIGNATURES = {
     "lsp_mc_maxpower": (_I32, [_P, _P, _I32, _P, _P, _P, _I32, ctypes.c_uint64, ctypes.c_uint64, _P, _P]),
     "lsp_window_features": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
     "lsp_normals": (_I32, [ctypes.c_uint64, ctypes.c_uint64, _I64, _P, _P]),
+    "lsp_model_param_count": (_I64, []),
+    "lsp_model_create": (_I32, [_I32, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "lsp_model_destroy": (_I32, [_P]),
+    "lsp_model_set_scalers": (_I32, [_P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "lsp_model_get_params": (_I32, [_P, _I32, _P, _I64]),
+    "lsp_model_set_params": (_I32, [_P, _I32, _P, _I64]),
+    "lsp_model_save": (_I32, [_P, ctypes.c_char_p, _I32]),
+    "lsp_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "lsp_mlp_forward": (_I32, [_P, _P, _I32, _P, _P]),
+    "lsp_mlp_grad": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _P]),
+    "lsp_mlp_adam_step": (_I32, [_P, _I32, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P]),
+    "lsp_mlp_gemm_nt": (_I32, [_P, _P, _P, _I32, _I32, _I32, _P]),
+    "lsp_fap_surrogate": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_float, _I32,
+                                 ctypes.c_uint64, _P]),
     "lsp_autotune": (_I32, [_I64, _I64, _I32, _P, ctypes.POINTER(lsp_tile), ctypes.POINTER(_D)]),
     "lsp_tune_lookup": (_I32, [_I64, _I64, _I32, ctypes.POINTER(lsp_tile)]),
     "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
@@ -377,3 +391,122 @@ def lsp_profile_read():
     buf = ctypes.create_string_buffer(256)
     _check(lib().lsp_profile_read(ctypes.byref(tot), ctypes.byref(n), buf, 256), "lsp_profile_read")
     return tot.value, int(n.value), buf.value.decode()
+
+
+# ---- false-alarm surrogate ------------------------------------------------------------
+
+N_QUANTILES = 9
+TAU = (0.5, 0.75, 0.9, 0.95, 0.975, 0.99, 0.995, 0.998, 0.999)
+
+
+def lsp_model_param_count() -> int:
+    return int(lib().lsp_model_param_count())
+
+
+def lsp_mlp_gemm_nt(A, B, out=None, stream=None):
+    """C = A B^T for device bfloat16 A [M, K], B [N, K] (multiples of 32); returns float32 C."""
+    torch = _torch()
+    _dev_tensor(A, torch.bfloat16, "A")
+    _dev_tensor(B, torch.bfloat16, "B")
+    M, K = A.shape
+    N = B.shape[0]
+    if out is None:
+        out = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    _check(lib().lsp_mlp_gemm_nt(_ptr(A), _ptr(B), _ptr(out), M, N, K, _stream_ptr(stream)), "lsp_mlp_gemm_nt")
+    return out
+
+
+class Model:
+    """An ensemble of surrogate networks living on the current device (lsp_model)."""
+
+    def __init__(self, members: int = 4, seed: int = 0, path: str = None):
+        h = ctypes.c_void_p()
+        if path is not None:
+            _check(lib().lsp_model_load(path.encode(), ctypes.byref(h)), "lsp_model_load")
+        else:
+            _check(lib().lsp_model_create(int(members), int(seed) & (2**64 - 1), ctypes.byref(h)),
+                   "lsp_model_create")
+        self.h = h
+        self._members = None
+
+    def close(self):
+        if self.h:
+            lib().lsp_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def members(self) -> int:
+        if self._members is None:
+            n = 0
+            buf = np.empty(lsp_model_param_count(), dtype=np.float32)
+            while lib().lsp_model_get_params(self.h, n, buf.ctypes.data_as(ctypes.c_void_p), buf.size) == LSP_OK:
+                n += 1
+            self._members = n
+        return self._members
+
+    def get_params(self, member: int) -> np.ndarray:
+        out = np.empty(lsp_model_param_count(), dtype=np.float32)
+        _check(lib().lsp_model_get_params(self.h, int(member), out.ctypes.data_as(ctypes.c_void_p), out.size),
+               "lsp_model_get_params")
+        return out
+
+    def set_params(self, member: int, params):
+        a = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+        _check(lib().lsp_model_set_params(self.h, int(member), a.ctypes.data_as(ctypes.c_void_p), a.size),
+               "lsp_model_set_params")
+
+    def set_scalers(self, feat_mean, feat_std, feat_zmax: float, q_mu: float, q_sigma: float):
+        m = np.ascontiguousarray(np.asarray(feat_mean, dtype=np.float32))
+        sd = np.ascontiguousarray(np.asarray(feat_std, dtype=np.float32))
+        _check(lib().lsp_model_set_scalers(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                           sd.ctypes.data_as(ctypes.c_void_p), float(feat_zmax), float(q_mu),
+                                           float(q_sigma)), "lsp_model_set_scalers")
+
+    def save(self, path: str, with_optimizer: bool = False):
+        _check(lib().lsp_model_save(self.h, path.encode(), 1 if with_optimizer else 0), "lsp_model_save")
+
+    def forward(self, feat, stream=None):
+        """Quantiles [members, B, 9] (device float32) of device features [B, 68]."""
+        torch = _torch()
+        _dev_tensor(feat, torch.float32, "feat")
+        B = feat.shape[0]
+        q = torch.empty((self.members, B, N_QUANTILES), dtype=torch.float32, device=feat.device)
+        _check(lib().lsp_mlp_forward(self.h, _ptr(feat), B, _ptr(q), _stream_ptr(stream)), "lsp_mlp_forward")
+        return q
+
+    def grad(self, member: int, feat, samples, want_grad=True, stream=None):
+        """(flat gradient or None, loss) of one member on a minibatch (device tensors)."""
+        torch = _torch()
+        _dev_tensor(feat, torch.float32, "feat")
+        _dev_tensor(samples, torch.float32, "samples")
+        B, R = samples.shape
+        g = torch.empty(lsp_model_param_count(), dtype=torch.float32, device=feat.device) if want_grad else None
+        loss = torch.empty(1, dtype=torch.float32, device=feat.device)
+        _check(lib().lsp_mlp_grad(self.h, int(member), _ptr(feat), _ptr(samples), int(R), int(B), _ptr(g),
+                                  _ptr(loss), _stream_ptr(stream)), "lsp_mlp_grad")
+        return g, loss
+
+    def adam_step(self, member: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(lib().lsp_mlp_adam_step(self.h, int(member), float(lr), float(beta1), float(beta2), float(eps),
+                                       _stream_ptr(stream)), "lsp_mlp_adam_step")
+
+    def fap(self, t, off, f_min, df, Nf, p_obs, max_sigma=0.005, mc_realizations=10000, seed=0, stream=None):
+        """(fap, sigma, used_mc) device tensors for observed maxima p_obs [n_pat]."""
+        torch = _torch()
+        _dev_tensor(t, torch.float64, "t")
+        _dev_tensor(p_obs, torch.float32, "p_obs")
+        off, f_min, df, Nf, n = _host_shape(off, f_min, df, Nf)
+        fap = torch.empty(n, dtype=torch.float32, device=t.device)
+        sig = torch.empty(n, dtype=torch.float32, device=t.device)
+        used = torch.empty(n, dtype=torch.int32, device=t.device)
+        hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        _check(lib().lsp_fap_surrogate(self.h, _ptr(t), hp(off), n, hp(f_min), hp(df), hp(Nf), _ptr(p_obs),
+                                       _ptr(fap), _ptr(sig), _ptr(used), float(max_sigma), int(mc_realizations),
+                                       int(seed) & (2**64 - 1), _stream_ptr(stream)), "lsp_fap_surrogate")
+        return fap, sig, used

@@ -1,0 +1,55 @@
+// mlp.h -- shapes and launchers of the surrogate network kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lsp {
+
+constexpr int kMlpIn = 68;        // features
+constexpr int kMlpInPad = 96;     // padded to the MFMA K step (32)
+constexpr int kMlpHidden = 256;
+constexpr int kMlpOut = 9;        // quantiles
+constexpr int kMlpOutPad = 32;    // padded to the 32-wide output tile
+constexpr int kMlpLayers = 4;
+
+// quantile levels of the maximum power
+constexpr float kTau[kMlpOut] = {0.5f, 0.75f, 0.9f, 0.95f, 0.975f, 0.99f, 0.995f, 0.998f, 0.999f};
+
+enum { GEMM_STORE = 0, GEMM_BIAS = 1, GEMM_BIAS_GELU = 2, GEMM_DGELU = 3 };
+
+struct GemmArgs {
+    const __bf16 *A;  // [M][K], row stride lda
+    int lda;
+    const __bf16 *B;  // [N][K], row stride ldb
+    int ldb;
+    int M, N, K;      // multiples of 32
+    int epi;          // GEMM_*
+    const float *bias;  // [N] (BIAS, BIAS_GELU)
+    const float *Z;     // [M][N] pre-activation, row stride ldz (DGELU)
+    int ldz;
+    float *C;         // FP32 result (pre-activation for BIAS_GELU), nullable
+    int ldc;
+    __bf16 *Cb;       // BF16 copy (GELU output for BIAS_GELU), nullable
+    int ldcb;
+    __bf16 *CbT;      // BF16 transposed copy [N][M], nullable
+    int ldcbT;
+};
+
+hipError_t launch_gemm_nt(const GemmArgs &g, hipStream_t s);
+hipError_t launch_features_in(const float *feat, int B, int Bp, const float *mean, const float *stdv, __bf16 *X,
+                              __bf16 *XT, float *zmax, hipStream_t s);
+hipError_t launch_quantiles(const float *raw, int B, int ldr, float mu, float sigma, float *q, hipStream_t s);
+hipError_t launch_pinball(const float *raw, int B, int Bp, int ldr, const float *y, int R, const float *tau, float mu,
+                          float sigma, float *loss_b, float *dR, __bf16 *dRb, __bf16 *dRbT, hipStream_t s);
+hipError_t launch_sum(const float *v, int n, float *out, hipStream_t s);
+hipError_t launch_colsum(const float *dZ, int B, int N, float *db, hipStream_t s);
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s);
+hipError_t launch_cast_weights(const float *W, int rows, int cols, __bf16 *Wb, __bf16 *WbT, hipStream_t s);
+hipError_t launch_fap(const float *q, int members, int B, const float *tau, const float *p_obs, float *fap,
+                      float *sigma, hipStream_t s);
+hipError_t launch_mc_fap(const float *pmax, int R, int B, const float *p_obs, const int32_t *idx, float *fap,
+                         float *sigma, hipStream_t s);
+
+}  // namespace lsp

@@ -1,0 +1,187 @@
+"""Training and validation of the false-alarm surrogate.
+
+Every numerical step runs in the library: Monte-Carlo maxima
+(lsp_mc_maxpower), window features (lsp_window_features), the network's
+forward, loss, backward and Adam (lsp_mlp_grad, lsp_mlp_adam_step) and the
+FAP with its Monte-Carlo fallback (lsp_fap_surrogate).  This module only
+chooses minibatches, learning rates and chunk sizes, and summarizes results.
+
+    python -m paper_1007_1658_amd.surrogate --out model.bin --report report.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+from . import Model, lsp_fap_analytic, lsp_mc_maxpower, lsp_window_features
+from . import synth
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_MODEL = os.path.join(_HERE, "models", "fap_surrogate_gfx950.bin")
+FAP_LEVELS = (0.001, 0.01, 0.05, 0.1)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _device_t(b: synth.Batch):
+    return _torch().from_numpy(np.ascontiguousarray(b.t)).cuda()
+
+
+def monte_carlo(b: synth.Batch, R: int, seed: int, stream_base: int = 0, max_values: int = 1 << 28):
+    """max Pn of R white-noise realizations on each pattern of b: device [n, R].
+
+    Patterns are processed in chunks holding at most max_values drawn values;
+    pattern p uses counter streams stream_base + p R + r whatever the chunking.
+    """
+    torch = _torch()
+    out = torch.empty((b.n, R), dtype=torch.float32, device="cuda")
+    p0 = 0
+    while p0 < b.n:
+        p1 = p0 + 1
+        while p1 < b.n and (b.off[p1 + 1] - b.off[p0]) * R <= max_values:
+            p1 += 1
+        sub = synth.subset(b, np.arange(p0, p1))
+        lsp_mc_maxpower(_device_t(sub), sub.off, sub.f_min, sub.df, sub.Nf, R, seed,
+                        stream_base=stream_base + p0 * R, out=out[p0:p1])
+        p0 = p1
+    return out
+
+
+def features(b: synth.Batch):
+    return lsp_window_features(_device_t(b), b.off, b.f_min, b.df, b.Nf)
+
+
+def fit_scalers(F: np.ndarray, Y: np.ndarray):
+    """Feature standardization, the accepted feature range and the quantile scale."""
+    mean = F.mean(axis=0)
+    std = np.maximum(F.std(axis=0), 1e-3)
+    zmax = float(np.abs((F - mean) / std).max()) * 1.25
+    return mean, std, zmax, float(Y.mean()), float(Y.std())
+
+
+def train(F, Y, members=4, steps=3000, batch=256, lr=2e-3, seed=0, log=None):
+    """Fits an ensemble on device features F [n, 68] and maxima Y [n, R]."""
+    torch = _torch()
+    n = F.shape[0]
+    mean, std, zmax, mu, sig = fit_scalers(F.cpu().numpy().astype(np.float64), Y.cpu().numpy())
+    model = Model(members=members, seed=seed)
+    model.set_scalers(mean, std, zmax, mu, sig)
+    history = []
+    for e in range(members):
+        g = np.random.default_rng([seed, e])
+        for step in range(steps):
+            idx = torch.from_numpy(g.choice(n, size=min(batch, n), replace=False)).cuda()
+            fb = F.index_select(0, idx).contiguous()
+            yb = Y.index_select(0, idx).contiguous()
+            _, loss = model.grad(e, fb, yb, want_grad=False)
+            lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
+            model.adam_step(e, lr_t)
+            if log is not None and (step % 500 == 0 or step == steps - 1):
+                history.append((e, step, float(loss.item())))
+                log(f"member {e} step {step} loss {history[-1][2]:.5f}")
+    return model, history
+
+
+def validate(model, b: synth.Batch, R=10000, seed=20260, levels=FAP_LEVELS, max_sigma=0.005, log=None):
+    """|FAP_surrogate - FAP_MC| at the MC quantiles for the given FAP levels, the
+    same for Eq. (3), the fallback rate and the speed against Monte Carlo."""
+    torch = _torch()
+    td = _device_t(b)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Y = monte_carlo(b, R, seed)
+    torch.cuda.synchronize()
+    t_mc = time.perf_counter() - t0
+    Ys, _ = torch.sort(Y, dim=1)
+    res = {"patterns": b.n, "R": R, "mc_seconds": t_mc, "levels": {}}
+    Nt = b.Nt
+    t_sur = 0.0
+    for a in levels:
+        k = max(0, int(math.ceil((1.0 - a) * R)) - 1)
+        p_obs = Ys[:, k].contiguous()
+        fap_mc = (Y >= p_obs[:, None]).float().mean(dim=1).cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fap_net, sig, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=1e9, mc_realizations=0)
+        torch.cuda.synchronize()
+        t_sur += time.perf_counter() - t0
+        fap_full, _, used = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=max_sigma,
+                                      mc_realizations=R, seed=seed + 1)
+        pn = p_obs.cpu().numpy()
+        fap_eq3 = np.array([lsp_fap_analytic(float(pn[i]), int(Nt[i]), int(b.Nf[i])) for i in range(b.n)])
+        net = np.abs(fap_net.cpu().numpy() - fap_mc)
+        full = np.abs(fap_full.cpu().numpy() - fap_mc)
+        eq3 = np.abs(fap_eq3 - fap_mc)
+        res["levels"][str(a)] = {
+            "net_max_abs_err": float(net.max()), "net_mean_abs_err": float(net.mean()),
+            "net_frac_within_0.005": float((net <= 0.005).mean()),
+            "with_fallback_max_abs_err": float(full.max()), "with_fallback_mean_abs_err": float(full.mean()),
+            "fallback_rate": float(used.float().mean().item()),
+            "eq3_max_abs_err": float(eq3.max()), "eq3_mean_abs_err": float(eq3.mean()),
+            "mc_standard_error": float(math.sqrt(a * (1 - a) / R)),
+        }
+        if log:
+            log(f"FAP {a}: net max {net.max():.4f} mean {net.mean():.5f}; with fallback max {full.max():.4f} "
+                f"(rate {res['levels'][str(a)]['fallback_rate']:.2f}); Eq.3 max {eq3.max():.3f} mean {eq3.mean():.4f}")
+    res["surrogate_seconds_per_level"] = t_sur / len(levels)
+    res["speedup_vs_mc"] = t_mc / max(res["surrogate_seconds_per_level"], 1e-9)
+    return res
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-patterns", type=int, default=2000)
+    ap.add_argument("--val-patterns", type=int, default=200)
+    ap.add_argument("--R", type=int, default=500)
+    ap.add_argument("--R-val", type=int, default=10000)
+    ap.add_argument("--members", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--batch", type=int, default=256)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--nt-max", type=int, default=20000)
+    ap.add_argument("--out", default="")
+    ap.add_argument("--report", default="")
+    args = ap.parse_args(argv)
+    log = lambda s: print(s, flush=True)
+    torch = _torch()
+    n_all = args.train_patterns + args.val_patterns
+    pats = synth.c4_patterns(n_all, nt_range=(200, args.nt_max))
+    tr = synth.subset(pats, np.arange(args.train_patterns))
+    va = synth.subset(pats, np.arange(args.train_patterns, n_all))
+    log(f"patterns: train {tr.n} ({tr.terms * args.R:.3g} MC terms), val {va.n} ({va.terms * args.R_val:.3g})")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = features(tr)
+    Y = monte_carlo(tr, args.R, seed=1)
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"training data in {t_data:.1f} s")
+    t0 = time.perf_counter()
+    model, hist = train(F, Y, members=args.members, steps=args.steps, batch=args.batch, lr=args.lr, log=log)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"trained in {t_train:.1f} s")
+    if args.out:
+        os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+        model.save(args.out)
+    res = validate(model, va, R=args.R_val, log=log)
+    res.update({"train_patterns": tr.n, "R_train": args.R, "data_seconds": t_data, "train_seconds": t_train,
+                "members": args.members, "steps": args.steps, "loss_history": hist})
+    log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
+    if args.report:
+        with open(args.report, "w") as f:
+            json.dump(res, f, indent=1)
+    model.close()
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

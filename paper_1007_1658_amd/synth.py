@@ -22,6 +22,12 @@ Workloads (times in days, frequencies in cycles per day):
   c3  Monte-Carlo batch: 4096 white-noise curves N(0, 1), Nt log-uniform in
       [200, 20000], own sorted times uniform over a baseline U[10, 1000] d,
       own grid df = 1/(4 T), f_min = df, Nf = 2 Nt.
+  c4  sampling patterns for the false-alarm surrogate: Nt log-uniform in
+      [200, 20000], baseline U[10, 1000] d, and one of three gap structures
+      (none; random gaps covering a fraction U[0, 0.5] of the baseline with
+      lengths log-uniform in [0.01 T, 0.2 T]; daily gaps with an observing
+      fraction U[0.3, 0.7] of each day); grid df = 1/(4 T), f_min = df,
+      Nf = 2 Nt.
   P   stand-in shaped like the paper's 150-d CoRoT series: Nt = 382,003 on a
       32-s grid with short random gaps, a dominant 0.18-d mode plus weaker
       terms plus noise; oversampling 4, high factor 2, Nf rounded up to a
@@ -164,6 +170,65 @@ def c3(seed_sub: int = 0, n_curves: int = 4096, nt_range=(200, 20000),
         x[a:b] = g.normal(0.0, 1.0, Nt[c]).astype(np.float32)
         df[c] = 1.0 / (f_over * _baseline(tc))
     return Batch(t, x, off, df.copy(), df, 2 * Nt, "c3")
+
+
+def _pattern_times(g: np.random.Generator, Nt: int, T: float, kind: int) -> np.ndarray:
+    """Nt sorted times over [0, T] with gap structure `kind` (0 none, 1 random, 2 daily)."""
+    if kind == 0:
+        return np.sort(g.uniform(0.0, T, Nt))
+    if kind == 1:
+        duty = g.uniform(0.0, 0.5)
+        # gap intervals until they cover about duty * T
+        gaps = []
+        covered = 0.0
+        while covered < duty * T:
+            L = math.exp(g.uniform(math.log(0.01 * T), math.log(0.2 * T)))
+            a = g.uniform(0.0, T)
+            gaps.append((a, a + L))
+            covered += L
+        keep = []
+        while sum(len(k) for k in keep) < Nt:
+            c = g.uniform(0.0, T, 2 * Nt)
+            ok = np.ones(c.size, dtype=bool)
+            for a, b in gaps:
+                ok &= ~((c >= a) & (c < b))
+            keep.append(c[ok])
+        t = np.concatenate(keep)[:Nt]
+        return np.sort(t)
+    frac = g.uniform(0.3, 0.7)
+    days = max(1, int(math.ceil(T)))
+    d = g.integers(0, days, Nt)
+    return np.sort(np.minimum(d + g.uniform(0.0, frac, Nt), T))
+
+
+def c4_patterns(n: int = 2200, seed_sub: int = 0, nt_range=(200, 20000), T_range=(10.0, 1000.0)) -> Batch:
+    """Sampling patterns of the surrogate workload (values are not used: zeros)."""
+    g = rng(4, seed_sub)
+    Nt = np.rint(np.exp(g.uniform(math.log(nt_range[0]), math.log(nt_range[1]), n))).astype(np.int64)
+    T = g.uniform(T_range[0], T_range[1], n)
+    kind = g.integers(0, 3, n)
+    off = np.zeros(n + 1, dtype=np.int64)
+    off[1:] = np.cumsum(Nt)
+    t = np.empty(int(off[-1]))
+    df = np.empty(n)
+    for p in range(n):
+        tp = _pattern_times(g, int(Nt[p]), float(T[p]), int(kind[p]))
+        t[off[p]:off[p + 1]] = tp
+        df[p] = 1.0 / (4.0 * _baseline(tp))
+    b = Batch(t, np.zeros(t.size, dtype=np.float32), off, df.copy(), df, 2 * Nt, "c4")
+    b.kind = kind  # type: ignore[attr-defined]
+    return b
+
+
+def subset(b: Batch, idx) -> Batch:
+    """The curves idx of a batch, as a batch of their own (CSR rebuilt)."""
+    idx = np.asarray(idx, dtype=np.int64)
+    Nt = b.off[idx + 1] - b.off[idx]
+    off = np.zeros(idx.size + 1, dtype=np.int64)
+    off[1:] = np.cumsum(Nt)
+    t = np.concatenate([b.t[b.off[i]:b.off[i + 1]] for i in idx]) if idx.size else np.zeros(0)
+    x = np.concatenate([b.x[b.off[i]:b.off[i + 1]] for i in idx]) if idx.size else np.zeros(0, np.float32)
+    return Batch(t, x, off, b.f_min[idx].copy(), b.df[idx].copy(), b.Nf[idx].copy(), b.name + "-sub")
 
 
 def paper_standin(seed_sub: int = 0) -> Curve:

@@ -1,0 +1,171 @@
+"""GPU parity of the surrogate network (BF16 MFMA) against the CPU reference."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref as R
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1007_1658_amd as lsp  # noqa: E402
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("M,N,K", [(32, 32, 32), (64, 96, 256), (256, 32, 96)])
+def test_gemm_nt_layout(M, N, K):
+    g = torch.Generator().manual_seed(M + N + K)
+    A = torch.randn(M, K, generator=g).to(torch.bfloat16)
+    B = torch.randn(N, K, generator=g).to(torch.bfloat16)
+    C = lsp.lsp_mlp_gemm_nt(A.cuda(), B.cuda()).cpu().numpy().astype(np.float64)
+    ref = A.double().numpy() @ B.double().numpy().T
+    assert np.max(np.abs(C - ref)) <= 1e-5 * np.abs(ref).max()
+
+
+def _model_and_data(B=48, nR=64, seed=5):
+    g = np.random.default_rng(seed)
+    m = lsp.Model(members=2, seed=seed)
+    params = [g.normal(0, 0.06, R.N_PARAMS).astype(np.float32) for _ in range(2)]
+    for e in range(2):
+        m.set_params(e, params[e])
+    mean = g.normal(0, 0.3, 68).astype(np.float32)
+    std = g.uniform(0.5, 2.0, 68).astype(np.float32)
+    m.set_scalers(mean, std, 50.0, 9.0, 1.3)
+    feat = (g.normal(0, 1, (B, 68)) * std + mean).astype(np.float32)
+    y = g.normal(9.0, 1.3, (B, nR)).astype(np.float32)
+    return m, params, feat, y, mean.astype(np.float64), std.astype(np.float64)
+
+
+def test_param_roundtrip_and_count():
+    m = lsp.Model(members=3, seed=1)
+    assert lsp.lsp_model_param_count() == R.N_PARAMS == 151561
+    assert m.members == 3
+    p = np.random.default_rng(0).normal(0, 1, R.N_PARAMS).astype(np.float32)
+    m.set_params(2, p)
+    assert np.array_equal(m.get_params(2), p)
+    m.close()
+
+
+def test_forward_matches_reference():
+    m, params, feat, y, mean, std = _model_and_data()
+    q = m.forward(torch.from_numpy(feat).cuda()).cpu().numpy()
+    for e in range(2):
+        ref = R.forward(params[e].astype(np.float64), feat, mean, std, 9.0, 1.3, bf=True)["q"]
+        assert rel_l2(q[e], ref) <= 1e-3
+        assert np.all(np.diff(q[e], axis=1) > 0)
+    m.close()
+
+
+def test_gradient_matches_reference():
+    m, params, feat, y, mean, std = _model_and_data()
+    g, loss = m.grad(1, torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda())
+    Lr, gr, _ = R.loss_and_grad(params[1].astype(np.float64), feat, y, mean, std, 9.0, 1.3, bf=True)
+    assert abs(loss.item() - Lr) <= 1e-4 * abs(Lr)
+    gg = g.cpu().numpy()
+    assert rel_l2(gg, gr) <= 1e-3
+    # per layer, so that a wrong layout in one product cannot hide in the total
+    o = 0
+    for (n_out, n_in) in R.SHAPES:
+        for sz in (n_out * n_in, n_out):
+            assert rel_l2(gg[o:o + sz], gr[o:o + sz]) <= 5e-3
+            o += sz
+    m.close()
+
+
+def test_adam_step_matches_reference():
+    m, params, feat, y, mean, std = _model_and_data()
+    g, _ = m.grad(0, torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda())
+    gh = g.cpu().numpy().astype(np.float64)
+    w0 = m.get_params(0).astype(np.float64)
+    m.adam_step(0, 1e-3)
+    w1 = m.get_params(0).astype(np.float64)
+    ref, mm, vv = R.adam_step(w0, gh, np.zeros_like(w0), np.zeros_like(w0), 1, lr=1e-3)
+    assert np.max(np.abs(w1 - ref)) <= 1e-6
+    # second step with the same minibatch
+    g2, _ = m.grad(0, torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda())
+    m.adam_step(0, 1e-3)
+    ref2, _, _ = R.adam_step(ref, g2.cpu().numpy().astype(np.float64), mm, vv, 2, lr=1e-3)
+    assert np.max(np.abs(m.get_params(0) - ref2)) <= 2e-6
+    m.close()
+
+
+def test_save_load_roundtrip(tmp_path):
+    m, params, feat, y, mean, std = _model_and_data()
+    f = str(tmp_path / "m.bin")
+    m.save(f)
+    m2 = lsp.Model(path=f)
+    for e in range(2):
+        assert np.array_equal(m2.get_params(e), m.get_params(e))
+    fd = torch.from_numpy(feat).cuda()
+    assert torch.equal(m.forward(fd), m2.forward(fd))
+    with pytest.raises(lsp.LspError) as ei:
+        lsp.Model(path=str(tmp_path / "missing.bin"))
+    assert ei.value.status == lsp.LSP_ERR_MODEL
+    m.close(); m2.close()
+
+
+def _patterns(n, seed):
+    g = np.random.default_rng(seed)
+    ts, off, fm, dfs, nfs = [], [0], [], [], []
+    for p in range(n):
+        nt = int(g.integers(60, 400))
+        t = np.sort(g.uniform(0, g.uniform(5, 60), nt))
+        df = 1.0 / (4 * (t[-1] - t[0]))
+        ts.append(t); off.append(off[-1] + nt); fm.append(df); dfs.append(df); nfs.append(2 * nt)
+    return np.concatenate(ts), np.array(off), np.array(fm), np.array(dfs), np.array(nfs)
+
+
+def test_fap_surrogate_and_fallback():
+    t, off, fm, df, nf = _patterns(8, 3)
+    td = torch.from_numpy(t).cuda()
+    feat = lsp.lsp_window_features(td, off, fm, df, nf)
+    m = lsp.Model(members=3, seed=2)
+    F = feat.cpu().numpy()
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, 8.0, 1.0)
+    p_obs = torch.linspace(6.0, 12.0, 8).cuda()
+    fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=10.0, mc_realizations=0)
+    q = m.forward(feat).cpu().numpy()
+    for b in range(8):
+        fe = [R.fap_from_quantiles(q[e, b], float(p_obs[b])) for e in range(3)]
+        assert abs(fap[b].item() - np.mean(fe)) <= 1e-5
+        assert abs(sig[b].item() - np.std(fe)) <= 1e-5
+    assert used.sum().item() == 0
+    # forced fallback: every pattern answered by Monte Carlo with the same draws as lsp_mc_maxpower
+    Rn = 256
+    fap2, sig2, used2 = m.fap(td, off, fm, df, nf, p_obs, max_sigma=0.0, mc_realizations=Rn, seed=77)
+    pm = lsp.lsp_mc_maxpower(td, off, fm, df, nf, Rn, seed=77).cpu().numpy()
+    assert used2.sum().item() == 8
+    expect = (pm >= p_obs.cpu().numpy()[:, None]).mean(axis=1)
+    assert np.allclose(fap2.cpu().numpy(), expect, atol=1e-7)
+    m.close()
+
+
+def test_short_training_reduces_loss():
+    t, off, fm, df, nf = _patterns(64, 4)
+    td = torch.from_numpy(t).cuda()
+    feat = lsp.lsp_window_features(td, off, fm, df, nf)
+    y = lsp.lsp_mc_maxpower(td, off, fm, df, nf, 64, seed=5)
+    F = feat.cpu().numpy()
+    Y = y.cpu().numpy()
+    m = lsp.Model(members=1, seed=9)
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, float(Y.mean()), float(Y.std()))
+    losses = []
+    for step in range(300):
+        _, loss = m.grad(0, feat, y, want_grad=False)
+        m.adam_step(0, 3e-3)
+        losses.append(loss.item())
+    # the per-pattern empirical quantiles minimize the in-sample pinball loss exactly: a floor
+    Ys = Y.astype(np.float64)
+    qf = np.stack([np.quantile(Ys, t, axis=1, method="inverted_cdf") for t in R.TAU], axis=1)
+    floor, _ = R.pinball(qf, Ys)
+    assert losses[-1] >= floor - 1e-6
+    assert losses[-1] - floor < 0.5 * (losses[0] - floor)
+    m.close()
