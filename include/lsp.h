@@ -198,20 +198,27 @@ lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out,
 
    Eq. (3) treats the Nf frequencies as independent; with oversampling they are
    not, and the number of independent frequencies has to be simulated (Section
-   6.2).  The surrogate learns, per sampling pattern, nine quantiles
-   (tau = 0.5, 0.75, 0.9, 0.95, 0.975, 0.99, 0.995, 0.998, 0.999) of the
-   maximum periodogram power of white noise, from Monte-Carlo maxima made by
-   lsp_mc_maxpower.  Network: features (68, standardized) -> 256 -> 256 -> 256 -> 9,
+   6.2).  The surrogate learns, per sampling pattern, the law of the maximum
+   periodogram power of white noise, from Monte-Carlo maxima made by
+   lsp_mc_maxpower.  Network: features (68, standardized) -> 256 -> 256 -> 256 -> 2,
    GELU (tanh form) after the first three layers; products on BF16 matrix
-   cores with FP32 accumulation; quantiles q_0 = mu + sigma r_0,
-   q_i = q_{i-1} + sigma softplus(r_i) (monotone).  A model is an ensemble of
-   `members` independently initialized networks; their spread is the
-   uncertainty.  All model entry points are synchronous with respect to the
-   model (one model = one user at a time; they lock it). */
+   cores with FP32 accumulation.  With the exponential-equivalent power
+   w(z) = -((Nt-3)/2) ln(1 - 2z/Nt) (a single frequency exceeds z with the
+   beta-law probability exp(-w), Section 2), the maximum is Gumbel in w:
+     P(max <= z) = exp(-exp(-u)),  u = (w(z) - ln Nf - m) / beta,
+     m = mu + sigma r_0,  beta = softplus(r_1 + ln(e - 1)),
+   so m = 0, beta = 1 is Eq. (3) with Nf independent frequencies.  Training
+   minimizes the negative log-likelihood of the Monte-Carlo maxima.  Reported
+   quantiles: tau = 0.5, 0.75, 0.9, 0.95, 0.975, 0.99, 0.995, 0.998, 0.999.
+   Nt and Nf are read back from the raw features (feat[64] = log10 Nt,
+   feat[67] = log10 Nf, as lsp_window_features writes them).  A model is an
+   ensemble of `members` independently initialized networks; their spread is
+   the uncertainty.  All model entry points are synchronous with respect to
+   the model (one model = one user at a time; they lock it). */
 typedef struct lsp_model lsp_model;
 
 /* Parameters per member (FP32 master weights): W1[256][68], b1[256],
-   W2[256][256], b2, W3[256][256], b3, W4[9][256], b4[9] in this flat order. */
+   W2[256][256], b2, W3[256][256], b3, W4[2][256], b4[2] in this flat order. */
 int64_t lsp_model_param_count(void);
 /* New model with uniform(+-1/sqrt(fan_in)) weights (0.1x for the last layer),
    zero biases, seeded per member from `seed`.  members in 1..16. */
@@ -219,7 +226,7 @@ lsp_status lsp_model_create(int32_t members, uint64_t seed, lsp_model **out);
 lsp_status lsp_model_destroy(lsp_model *m);
 /* Feature standardization (host FP32 [68] mean and std > 0), the largest
    |standardized feature| accepted before the Monte-Carlo fallback, and the
-   quantile scale (mu, sigma > 0). */
+   location scale (mu, sigma > 0) of the head. */
 lsp_status lsp_model_set_scalers(lsp_model *m, const float *feat_mean, const float *feat_std,
                                  float feat_zmax, float q_mu, float q_sigma);
 /* FP32 master parameters of one member, flat order above (host [n], n must
@@ -232,12 +239,13 @@ lsp_status lsp_model_set_params(lsp_model *m, int32_t member, const float *host,
 lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_optimizer);
 lsp_status lsp_model_load(const char *path, lsp_model **out);
 
-/* Quantiles of every member: feat device FP32 [B][68] (raw features),
-   q device FP32 [members][B][9].  Asynchronous on stream. */
+/* The nine quantiles of the maximum under every member's law: feat device
+   FP32 [B][68] (raw features), q device FP32 [members][B][9].  Asynchronous
+   on stream. */
 lsp_status lsp_mlp_forward(lsp_model *m, const float *feat, int32_t B, float *q, void *stream);
-/* Forward, pinball loss against R Monte-Carlo maxima per pattern
-   (samples device FP32 [B][R]),
-     L = 1/(9B) sum_b sum_i 1/R sum_r rho_tau_i(y_br - q_bi),  rho_tau(u) = u (tau - [u < 0]),
+/* Forward, negative log-likelihood of R Monte-Carlo maxima per pattern
+   (samples device FP32 [B][R], each below Nt/2),
+     L = 1/(B R) sum_b sum_r [ln beta_b + u_br + exp(-u_br)],
    and backward of one member.  grad (device FP32 [param_count], flat order)
    and loss (device FP32 [1]) may be NULL; the gradient also stays inside the
    model for lsp_mlp_adam_step.  Asynchronous. */
@@ -254,10 +262,9 @@ lsp_status lsp_mlp_gemm_nt(const void *A, const void *B, float *C, int32_t M, in
                            void *stream);
 
 /* FAP of observed maxima: for each pattern p (as in lsp_mc_maxpower, times
-   sorted, Nt >= 4), fap[p] = P(max Pn of white noise >= p_obs[p]).  The CDF
-   of the maximum is interpolated from each member's quantiles, linearly in
-   the Gumbel variate -ln(-ln tau) (extended along the end segments); fap is
-   the members' mean and fap_sigma their standard deviation.  Patterns with
+   sorted, Nt >= 4), fap[p] = P(max Pn of white noise >= p_obs[p]) =
+   1 - exp(-exp(-u)) under each member's law; fap is the members' mean and
+   fap_sigma their standard deviation.  Patterns with
    fap_sigma > max_sigma, or with a standardized feature beyond the model's
    range, are answered by Monte Carlo instead (mc_realizations draws, key
    `seed`; fap = fraction of maxima >= p_obs, fap_sigma its binomial

@@ -128,85 +128,128 @@ hipError_t launch_features_in(const float *feat, int B, int Bp, const float *mea
     return hipGetLastError();
 }
 
-__device__ __forceinline__ float softplus(float r) { return r > 20.f ? r : log1pf(expf(r)); }
-__device__ __forceinline__ float sigmoid(float r) { return 1.f / (1.f + expf(-r)); }
+// ---------------------------------------------------------------------------
+// The law of the maximum.  A single frequency's normalized power z exceeds a
+// level with the beta-law probability (1 - 2z/Nt)^((Nt-3)/2) = exp(-w(z)) of
+// white noise (Section 2, after Eq. (3)); the maximum over the grid is taken
+// as Gumbel in w with location ln Nf + m and scale beta:
+//   P(max <= z) = exp(-exp(-u)),  u = (w(z) - ln Nf - m) / beta,
+//   m = mu + sigma r_0,  beta = softplus(r_1 + ln(e - 1)).
+// m = 0, beta = 1 is Eq. (3) with Nf independent frequencies (in its Poisson
+// limit).  Per-pattern arithmetic is FP64.
 
-// monotone head: q0 = mu + sigma r0, q_i = q_{i-1} + sigma softplus(r_i)
-__device__ __forceinline__ void head(const float *raw, float mu, float sigma, float *q)
+constexpr double kBetaShift = 0.54132485461291810;  // ln(e - 1): beta = 1 at r_1 = 0
+
+__device__ __forceinline__ double softplus_d(double r) { return r > 30.0 ? r : log1p(exp(r)); }
+__device__ __forceinline__ double sigmoid_d(double r) { return 1.0 / (1.0 + exp(-r)); }
+
+// the nine reported quantile levels tau
+__device__ __forceinline__ double quantile_level(int i)
 {
-    float acc = mu + sigma * raw[0];
-    q[0] = acc;
-    for (int i = 1; i < kMlpOut; ++i) {
-        acc += sigma * softplus(raw[i]);
-        q[i] = acc;
+    switch (i) {
+    case 0: return 0.5;
+    case 1: return 0.75;
+    case 2: return 0.9;
+    case 3: return 0.95;
+    case 4: return 0.975;
+    case 5: return 0.99;
+    case 6: return 0.995;
+    case 7: return 0.998;
+    default: return 0.999;
     }
 }
 
-__global__ void __launch_bounds__(256) quantiles_kernel(const float *raw, int B, int ldr, float mu, float sigma,
-                                                        float *q)
+struct PatternSize {
+    double Nt, lnNf;
+};
+
+__device__ __forceinline__ PatternSize pattern_size(const float *feat, int b)
+{
+    PatternSize p;
+    p.Nt = rint(pow(10.0, (double)feat[(size_t)b * kMlpIn + kFeatLogNt]));
+    p.lnNf = log(rint(pow(10.0, (double)feat[(size_t)b * kMlpIn + kFeatLogNf])));
+    return p;
+}
+
+// exponential-equivalent power of z, and its inverse
+__device__ __forceinline__ double w_of(double z, double Nt)
+{
+    return -0.5 * (Nt - 3.0) * log1p(-fmin(2.0 * z / Nt, 1.0 - 1e-15));
+}
+__device__ __forceinline__ double z_of(double w, double Nt) { return -0.5 * Nt * expm1(-2.0 * w / (Nt - 3.0)); }
+
+__global__ void __launch_bounds__(256) head_kernel(const float *raw, int ldr, const float *feat, int B, float mu,
+                                                   float sigma, float *law, float *q)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    head(raw + (size_t)b * ldr, mu, sigma, q + (size_t)b * kMlpOut);
+    const double m = (double)mu + (double)sigma * (double)raw[(size_t)b * ldr];
+    const double beta = softplus_d((double)raw[(size_t)b * ldr + 1] + kBetaShift);
+    if (law) {
+        law[(size_t)b * 2] = (float)m;
+        law[(size_t)b * 2 + 1] = (float)beta;
+    }
+    if (q) {
+        const PatternSize ps = pattern_size(feat, b);
+        for (int i = 0; i < kQuantiles; ++i) {
+            const double w = ps.lnNf + m + beta * -log(-log(quantile_level(i)));
+            q[(size_t)b * kQuantiles + i] = (float)z_of(w, ps.Nt);
+        }
+    }
 }
 
-hipError_t launch_quantiles(const float *raw, int B, int ldr, float mu, float sigma, float *q, hipStream_t s)
+hipError_t launch_head(const float *raw, int ldr, const float *feat, int B, float mu, float sigma, float *law, float *q,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(quantiles_kernel, dim3((B + 255) / 256), dim3(256), 0, s, raw, B, ldr, mu, sigma, q);
+    hipLaunchKernelGGL(head_kernel, dim3((B + 255) / 256), dim3(256), 0, s, raw, ldr, feat, B, mu, sigma, law, q);
     return hipGetLastError();
 }
 
-// Pinball loss of the nine quantiles against R Monte-Carlo maxima per pattern,
-//   L = 1/(9 B) sum_b sum_i 1/R sum_r rho_tau_i(y_br - q_bi),  rho_tau(u) = u (tau - [u < 0]),
-// its gradient through the head, written as dRaw in FP32 and BF16 (both layouts).
-__global__ void __launch_bounds__(256) pinball_kernel(const float *raw, int B, int Bp, int ldr, const float *y, int R,
-                                                      const float *tau, float mu, float sigma, float *loss_b,
-                                                      float *dR, __bf16 *dRb, __bf16 *dRbT)
+// Negative log-likelihood of R Monte-Carlo maxima per pattern under the law,
+//   L = 1/(B R) sum_b sum_r [ln beta + u + exp(-u)],  u = (w(y) - ln Nf - m) / beta,
+// and its gradient through the head, written as dRaw in FP32 and BF16 (both layouts).
+__global__ void __launch_bounds__(256) gumbel_nll_kernel(const float *raw, int ldr, const float *feat, int B, int Bp,
+                                                         const float *y, int R, float mu, float sigma, float *loss_b,
+                                                         float *dR, __bf16 *dRb, __bf16 *dRbT)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= Bp) return;
-    float dr[kMlpOutPad];
-    for (int i = 0; i < kMlpOutPad; ++i) dr[i] = 0.f;
-    float lb = 0.f;
+    float dr0 = 0.f, dr1 = 0.f, lb = 0.f;
     if (b < B) {
-        const float *rb = raw + (size_t)b * ldr;
-        float q[kMlpOut];
-        head(rb, mu, sigma, q);
-        float dq[kMlpOut];
-        const float scale = 1.0f / (float)(kMlpOut * B);
-        for (int i = 0; i < kMlpOut; ++i) {
-            double lsum = 0.0;
-            int below = 0;
-            for (int r = 0; r < R; ++r) {
-                const float u = y[(size_t)b * R + r] - q[i];
-                below += (u < 0.f) ? 1 : 0;
-                lsum += (double)(u * (tau[i] - (u < 0.f ? 1.f : 0.f)));
-            }
-            lb += (float)(lsum / (double)R);
-            dq[i] = ((float)below / (float)R - tau[i]) * scale;
+        const double r1 = (double)raw[(size_t)b * ldr + 1] + kBetaShift;
+        const double m = (double)mu + (double)sigma * (double)raw[(size_t)b * ldr];
+        const double beta = softplus_d(r1);
+        const PatternSize ps = pattern_size(feat, b);
+        double su = 0.0, se = 0.0, sue = 0.0;  // sums of u, exp(-u), u exp(-u)
+        for (int r = 0; r < R; ++r) {
+            const double u = (w_of((double)y[(size_t)b * R + r], ps.Nt) - ps.lnNf - m) / beta;
+            const double e = exp(-u);
+            su += u;
+            se += e;
+            sue += u * e;
         }
-        lb *= scale;
-        // back through the head: q_i depends on r_0 (slope sigma) and on r_j, j <= i
-        float tail = 0.f;
-        for (int i = kMlpOut - 1; i >= 1; --i) {
-            tail += dq[i];
-            dr[i] = tail * sigma * sigmoid(rb[i]);
-        }
-        dr[0] = (tail + dq[0]) * sigma;
+        const double scale = 1.0 / ((double)B * (double)R);
+        lb = (float)(((double)R * log(beta) + su + se) * scale);
+        const double dm = -((double)R - se) / beta * scale;          // dL/dm
+        const double db = ((double)R - su + sue) / beta * scale;      // dL/dbeta
+        dr0 = (float)(dm * (double)sigma);
+        dr1 = (float)(db * sigmoid_d(r1));
     }
     if (loss_b && b < B) loss_b[b] = lb;
     for (int i = 0; i < kMlpOutPad; ++i) {
-        dR[(size_t)b * kMlpOutPad + i] = dr[i];
-        dRb[(size_t)b * kMlpOutPad + i] = to_bf16(dr[i]);
-        dRbT[(size_t)i * Bp + b] = to_bf16(dr[i]);
+        const float d = (i == 0) ? dr0 : (i == 1 ? dr1 : 0.f);
+        dR[(size_t)b * kMlpOutPad + i] = d;
+        dRb[(size_t)b * kMlpOutPad + i] = to_bf16(d);
+        dRbT[(size_t)i * Bp + b] = to_bf16(d);
     }
 }
 
-hipError_t launch_pinball(const float *raw, int B, int Bp, int ldr, const float *y, int R, const float *tau, float mu,
-                          float sigma, float *loss_b, float *dR, __bf16 *dRb, __bf16 *dRbT, hipStream_t s)
+hipError_t launch_gumbel_nll(const float *raw, int ldr, const float *feat, int B, int Bp, const float *y, int R,
+                             float mu, float sigma, float *loss_b, float *dR, __bf16 *dRb, __bf16 *dRbT,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(pinball_kernel, dim3((Bp + 255) / 256), dim3(256), 0, s, raw, B, Bp, ldr, y, R, tau, mu, sigma,
-                       loss_b, dR, dRb, dRbT);
+    hipLaunchKernelGGL(gumbel_nll_kernel, dim3((Bp + 255) / 256), dim3(256), 0, s, raw, ldr, feat, B, Bp, y, R, mu,
+                       sigma, loss_b, dR, dRb, dRbT);
     return hipGetLastError();
 }
 
@@ -288,26 +331,20 @@ hipError_t launch_cast_weights(const float *W, int rows, int cols, __bf16 *Wb, _
     return hipGetLastError();
 }
 
-// FAP of an observed maximum from predicted quantiles, per member: the CDF of
-// the maximum is interpolated linearly in the Gumbel reduced variate
-// y = -ln(-ln tau) against q (extrapolated along the end segments), and
-// FAP = 1 - exp(-exp(-y)).  Then mean and spread over members.
-__global__ void __launch_bounds__(256) fap_kernel(const float *q, int members, int B, const float *tau,
+// FAP of an observed maximum under each member's law, 1 - exp(-exp(-u)),
+// then the members' mean and spread.
+__global__ void __launch_bounds__(256) fap_kernel(const float *law, int members, int B, const float *feat,
                                                   const float *p_obs, float *fap, float *sigma)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
-    double yl[kMlpOut];
-    for (int i = 0; i < kMlpOut; ++i) yl[i] = -log(-log((double)tau[i]));
-    const double p = (double)p_obs[b];
+    const PatternSize ps = pattern_size(feat, b);
+    const double w = w_of((double)p_obs[b], ps.Nt) - ps.lnNf;
     double s1 = 0.0, s2 = 0.0;
     for (int e = 0; e < members; ++e) {
-        const float *qb = q + ((size_t)e * B + b) * kMlpOut;
-        int i = 0;
-        while (i < kMlpOut - 2 && p > (double)qb[i + 1]) ++i;  // segment [i, i+1], ends extended
-        const double dq = fmax((double)qb[i + 1] - (double)qb[i], 1e-12);
-        const double y = yl[i] + (p - (double)qb[i]) * (yl[i + 1] - yl[i]) / dq;
-        const double f = -expm1(-exp(-y));
+        const float *lw = law + ((size_t)e * B + b) * 2;
+        const double u = (w - (double)lw[0]) / (double)lw[1];
+        const double f = -expm1(-exp(-u));
         s1 += f;
         s2 += f * f;
     }
@@ -316,10 +353,10 @@ __global__ void __launch_bounds__(256) fap_kernel(const float *q, int members, i
     sigma[b] = (float)sqrt(fmax(s2 / members - mean * mean, 0.0));
 }
 
-hipError_t launch_fap(const float *q, int members, int B, const float *tau, const float *p_obs, float *fap,
+hipError_t launch_fap(const float *law, int members, int B, const float *feat, const float *p_obs, float *fap,
                       float *sigma, hipStream_t s)
 {
-    hipLaunchKernelGGL(fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, q, members, B, tau, p_obs, fap, sigma);
+    hipLaunchKernelGGL(fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, law, members, B, feat, p_obs, fap, sigma);
     return hipGetLastError();
 }
 

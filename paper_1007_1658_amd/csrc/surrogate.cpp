@@ -5,8 +5,10 @@
 // The maximum of a white-noise periodogram over Nf correlated frequencies has
 // no closed-form law (Eq. (3) assumes independent frequencies, Section 3, and
 // Section 6.2 points to simulations for the effective number); the surrogate
-// learns nine quantiles of that maximum from Monte-Carlo periodograms this
-// library generates, and keeps plain Monte Carlo as its fallback.
+// learns the law of that maximum (a Gumbel law in the exponential-equivalent
+// power, two numbers per pattern, from which the nine reported quantiles and
+// the FAP follow) from Monte-Carlo periodograms this library generates, and
+// keeps plain Monte Carlo as its fallback.
 #include <array>
 #include <cmath>
 #include <cstdio>
@@ -37,7 +39,7 @@ constexpr LayerShape kL[kMlpLayers] = {
      256 * 96 + 256 + 2 * 65536 + 2 * 256 + 32 * 256},
 };
 constexpr size_t kPadded = 256 * 96 + 256 + 2 * (65536 + 256) + 32 * 256 + 32;
-constexpr int64_t kParams = 256 * 68 + 256 + 2 * (65536 + 256) + 9 * 256 + 9;  // unpadded, per member
+constexpr int64_t kParams = 256 * 68 + 256 + 2 * (65536 + 256) + kMlpOut * 256 + kMlpOut;  // unpadded, per member
 
 size_t round32(size_t v) { return (v + 31) / 32 * 32; }
 
@@ -56,7 +58,7 @@ struct lsp_model {
     std::vector<float *> P, G, M1, M2;
     std::vector<int> step;
     std::vector<std::array<__bf16 *, kMlpLayers>> Wb, WbT;
-    float *d_mean = nullptr, *d_std = nullptr, *d_tau = nullptr;
+    float *d_mean = nullptr, *d_std = nullptr;
     // activation workspace for batches up to cap rows
     size_t cap = 0;
     __bf16 *X = nullptr, *XT = nullptr;
@@ -67,7 +69,7 @@ struct lsp_model {
     __bf16 *dZb[2] = {nullptr, nullptr}, *dZbT[2] = {nullptr, nullptr};
     float *dR = nullptr;
     __bf16 *dRb = nullptr, *dRbT = nullptr;
-    float *loss_b = nullptr, *zmax = nullptr, *q = nullptr;
+    float *loss_b = nullptr, *zmax = nullptr, *law = nullptr;  // law: [members][B][2] (m, beta)
     std::vector<void *> ws;  // everything of the activation workspace, for freeing
     std::mutex mu;
 };
@@ -114,7 +116,7 @@ hipError_t ensure_ws(lsp_model *m, size_t Bp, hipStream_t s)
     if (e == hipSuccess) e = dalloc(&m->dRbT, Bp * kMlpOutPad, &m->ws);
     if (e == hipSuccess) e = dalloc(&m->loss_b, Bp, &m->ws);
     if (e == hipSuccess) e = dalloc(&m->zmax, Bp, &m->ws);
-    if (e == hipSuccess) e = dalloc(&m->q, (size_t)m->members * Bp * kMlpOut, &m->ws);
+    if (e == hipSuccess) e = dalloc(&m->law, (size_t)m->members * Bp * 2, &m->ws);
     m->cap = (e == hipSuccess) ? Bp : 0;
     return e;
 }
@@ -170,11 +172,12 @@ hipError_t forward_member(lsp_model *m, int e_, int Bp, hipStream_t s)
     return launch_gemm_nt(g, s);
 }
 
-// pinball loss and backward of member e into m->G[e]; loss (device scalar) optional
-hipError_t backward_member(lsp_model *m, int e_, int B, int Bp, const float *y, int R, float *loss, hipStream_t s)
+// likelihood loss and backward of member e into m->G[e]; loss (device scalar) optional
+hipError_t backward_member(lsp_model *m, int e_, const float *feat, int B, int Bp, const float *y, int R, float *loss,
+                           hipStream_t s)
 {
-    hipError_t e = launch_pinball(m->raw, B, Bp, kMlpOutPad, y, R, m->d_tau, m->q_mu, m->q_sigma, m->loss_b, m->dR,
-                                  m->dRb, m->dRbT, s);
+    hipError_t e = launch_gumbel_nll(m->raw, kMlpOutPad, feat, B, Bp, y, R, m->q_mu, m->q_sigma, m->loss_b, m->dR,
+                                     m->dRb, m->dRbT, s);
     if (e == hipSuccess && loss) e = launch_sum(m->loss_b, B, loss, s);
     float *G = m->G[e_];
     // layer 4: dW4 = dR^T H3, db4 = colsum dR, dZ3 = (dR W4) * gelu'(Z3)
@@ -262,8 +265,6 @@ lsp_status alloc_model(lsp_model *m)
     }
     if (e == hipSuccess) e = dalloc(&m->d_mean, kMlpIn, nullptr);
     if (e == hipSuccess) e = dalloc(&m->d_std, kMlpIn, nullptr);
-    if (e == hipSuccess) e = dalloc(&m->d_tau, kMlpOut, nullptr);
-    if (e == hipSuccess) e = hipMemcpy(m->d_tau, kTau, sizeof(kTau), hipMemcpyHostToDevice);
     return e == hipSuccess ? LSP_OK : fail(e, "model allocation");
 }
 
@@ -274,7 +275,7 @@ lsp_status upload_scalers(lsp_model *m)
     return e == hipSuccess ? LSP_OK : fail(e, "scaler upload");
 }
 
-const char kMagic[16] = "MI355LSP-FAP-1";
+const char kMagic[16] = "MI355LSP-FAP-2";
 
 }  // namespace
 
@@ -339,7 +340,6 @@ lsp_status lsp_model_destroy(lsp_model *m)
     for (void *p : m->ws) hipFree(p);
     hipFree(m->d_mean);
     hipFree(m->d_std);
-    hipFree(m->d_tau);
     delete m;
     return LSP_OK;
 }
@@ -389,7 +389,8 @@ lsp_status lsp_mlp_forward(lsp_model *m, const float *feat, int32_t B, float *q,
     for (int i = 0; i < m->members && e == hipSuccess; ++i) {
         e = forward_member(m, i, Bp, s);
         if (e == hipSuccess)
-            e = launch_quantiles(m->raw, B, kMlpOutPad, m->q_mu, m->q_sigma, q + (size_t)i * B * kMlpOut, s);
+            e = launch_head(m->raw, kMlpOutPad, feat, B, m->q_mu, m->q_sigma, nullptr, q + (size_t)i * B * kQuantiles,
+                            s);
     }
     return e == hipSuccess ? LSP_OK : fail(e, "lsp_mlp_forward");
 }
@@ -405,7 +406,7 @@ lsp_status lsp_mlp_grad(lsp_model *m, int32_t member, const float *feat, const f
     hipError_t e = ensure_ws(m, Bp, s);
     if (e == hipSuccess) e = launch_features_in(feat, B, Bp, m->d_mean, m->d_std, m->X, m->XT, nullptr, s);
     if (e == hipSuccess) e = forward_member(m, member, Bp, s);
-    if (e == hipSuccess) e = backward_member(m, member, B, Bp, samples, R, loss, s);
+    if (e == hipSuccess) e = backward_member(m, member, feat, B, Bp, samples, R, loss, s);
     if (e == hipSuccess && grad) e = copy_params(m->G[member], grad, true, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? LSP_OK : fail(e, "lsp_mlp_grad");
 }
@@ -542,7 +543,7 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
     hipError_t he = hipMalloc(&feat, sizeof(float) * kFeatures * (size_t)n_pat);
     if (he != hipSuccess) return fail(he, "feature buffer");
     lsp_status st = lsp_window_features(t, off, n_pat, f_min, df, Nf, feat, stream);
-    // 2. quantiles from every member, 3. FAP and its spread
+    // 2. the law from every member, 3. FAP and its spread
     std::vector<float> hz((size_t)n_pat), hs((size_t)n_pat);
     if (st == LSP_OK) {
         std::lock_guard<std::mutex> lock(m->mu);
@@ -552,10 +553,10 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
         for (int i = 0; i < m->members && he == hipSuccess; ++i) {
             he = forward_member(m, i, Bp, s);
             if (he == hipSuccess)
-                he = launch_quantiles(m->raw, n_pat, kMlpOutPad, m->q_mu, m->q_sigma,
-                                      m->q + (size_t)i * n_pat * kMlpOut, s);
+                he = launch_head(m->raw, kMlpOutPad, feat, n_pat, m->q_mu, m->q_sigma,
+                                 m->law + (size_t)i * n_pat * 2, nullptr, s);
         }
-        if (he == hipSuccess) he = launch_fap(m->q, m->members, n_pat, m->d_tau, p_obs, fap, fap_sigma, s);
+        if (he == hipSuccess) he = launch_fap(m->law, m->members, n_pat, feat, p_obs, fap, fap_sigma, s);
         if (he == hipSuccess) he = hipMemcpyAsync(hz.data(), m->zmax, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
         if (he == hipSuccess)
             he = hipMemcpyAsync(hs.data(), fap_sigma, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);

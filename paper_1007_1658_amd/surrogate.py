@@ -60,34 +60,68 @@ def features(b: synth.Batch):
     return lsp_window_features(_device_t(b), b.off, b.f_min, b.df, b.Nf)
 
 
+def law_targets(F: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """w(y) - ln Nf of every Monte-Carlo maximum, w(z) = -((Nt-3)/2) ln(1 - 2z/Nt),
+    with Nt and Nf read from the raw features as the library reads them."""
+    F = np.asarray(F, dtype=np.float64)
+    nt = np.rint(10.0 ** F[:, 64])[:, None]
+    nf = np.rint(10.0 ** F[:, 67])[:, None]
+    return -((nt - 3.0) / 2.0) * np.log1p(-2.0 * np.asarray(Y, dtype=np.float64) / nt) - np.log(nf)
+
+
 def fit_scalers(F: np.ndarray, Y: np.ndarray):
-    """Feature standardization, the accepted feature range and the quantile scale."""
+    """Feature standardization, the accepted feature range and the head's
+    location scale (moment estimates of the Gumbel location and of the spread
+    of the targets)."""
     mean = F.mean(axis=0)
     std = np.maximum(F.std(axis=0), 1e-3)
     zmax = float(np.abs((F - mean) / std).max()) * 1.25
-    return mean, std, zmax, float(Y.mean()), float(Y.std())
+    W = law_targets(F, Y)
+    beta = W.std() * np.sqrt(6.0) / np.pi
+    return mean, std, zmax, float(W.mean() - 0.5772156649 * beta), float(W.std())
 
 
-def train(F, Y, members=4, steps=3000, batch=256, lr=2e-3, seed=0, log=None):
-    """Fits an ensemble on device features F [n, 68] and maxima Y [n, R]."""
+def train(F, Y, members=4, steps=1500, batch=256, lr=2e-3, seed=0, holdout=0.1, eval_every=50, log=None):
+    """Fits an ensemble on device features F [n, 68] and maxima Y [n, R].
+
+    A seeded `holdout` fraction of the patterns is kept out of the minibatches;
+    every `eval_every` steps its loss is measured and each member keeps the
+    parameters of its best held-out loss (early stopping)."""
     torch = _torch()
     n = F.shape[0]
-    mean, std, zmax, mu, sig = fit_scalers(F.cpu().numpy().astype(np.float64), Y.cpu().numpy())
+    perm = np.random.default_rng([seed, 99]).permutation(n)
+    n_ho = int(round(holdout * n)) if holdout > 0 else 0
+    tr_idx, ho_idx = perm[n_ho:], perm[:n_ho]
+    Fh, Yh = F.cpu().numpy().astype(np.float64), Y.cpu().numpy()
+    mean, std, zmax, mu, sig = fit_scalers(Fh[tr_idx], Yh[tr_idx])
     model = Model(members=members, seed=seed)
     model.set_scalers(mean, std, zmax, mu, sig)
+    if n_ho:
+        ho = torch.from_numpy(ho_idx).cuda()
+        F_ho, Y_ho = F.index_select(0, ho).contiguous(), Y.index_select(0, ho).contiguous()
     history = []
     for e in range(members):
         g = np.random.default_rng([seed, e])
-        for step in range(steps):
-            idx = torch.from_numpy(g.choice(n, size=min(batch, n), replace=False)).cuda()
+        best = (math.inf, None, -1)
+        for step in range(steps + 1):
+            if n_ho and (step % eval_every == 0 or step == steps):
+                _, hl = model.grad(e, F_ho, Y_ho, want_grad=False)
+                hl = float(hl.item())
+                if hl < best[0]:
+                    best = (hl, model.get_params(e), step)
+            if step == steps:
+                break
+            idx = torch.from_numpy(tr_idx[g.choice(tr_idx.size, size=min(batch, tr_idx.size), replace=False)]).cuda()
             fb = F.index_select(0, idx).contiguous()
             yb = Y.index_select(0, idx).contiguous()
             _, loss = model.grad(e, fb, yb, want_grad=False)
             lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * step / steps)) + 1e-5
             model.adam_step(e, lr_t)
-            if log is not None and (step % 500 == 0 or step == steps - 1):
-                history.append((e, step, float(loss.item())))
-                log(f"member {e} step {step} loss {history[-1][2]:.5f}")
+            if log is not None and (step % 250 == 0 or step == steps - 1):
+                log(f"member {e} step {step} loss {float(loss.item()):.5f} held-out best {best[0]:.5f} at {best[2]}")
+        if best[1] is not None:
+            model.set_params(e, best[1])
+        history.append({"member": e, "best_step": best[2], "heldout_loss": best[0]})
     return model, history
 
 
@@ -144,7 +178,7 @@ def main(argv=None):
     ap.add_argument("--R", type=int, default=500)
     ap.add_argument("--R-val", type=int, default=10000)
     ap.add_argument("--members", type=int, default=4)
-    ap.add_argument("--steps", type=int, default=3000)
+    ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--nt-max", type=int, default=20000)
@@ -175,8 +209,8 @@ def main(argv=None):
         model.save(args.out)
     res = validate(model, va, R=args.R_val, log=log)
     res.update({"train_patterns": tr.n, "R_train": args.R, "data_seconds": t_data, "train_seconds": t_train,
-                "members": args.members, "steps": args.steps, "loss_history": hist})
-    log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
+                "members": args.members, "steps": args.steps, "early_stopping": hist})
+    log(json.dumps(res))
     if args.report:
         with open(args.report, "w") as f:
             json.dump(res, f, indent=1)

@@ -1,6 +1,7 @@
 """GPU parity of the surrogate network (BF16 MFMA) against the CPU reference."""
 import numpy as np
 import pytest
+from scipy import stats
 
 from oracle import mlp_ref as R
 import oracle
@@ -38,15 +39,22 @@ def _model_and_data(B=48, nR=64, seed=5):
         m.set_params(e, params[e])
     mean = g.normal(0, 0.3, 68).astype(np.float32)
     std = g.uniform(0.5, 2.0, 68).astype(np.float32)
-    m.set_scalers(mean, std, 50.0, 9.0, 1.3)
-    feat = (g.normal(0, 1, (B, 68)) * std + mean).astype(np.float32)
+    m.set_scalers(mean, std, 50.0, MU, SIGMA)
+    feat = g.normal(0, 1, (B, 68)) * std + mean
+    nt = np.rint(10 ** g.uniform(np.log10(200), np.log10(20000), B))
+    feat[:, 64] = np.log10(nt)        # the slots the head reads Nt and Nf from
+    feat[:, 67] = np.log10(2 * nt)
+    feat = feat.astype(np.float32)
     y = g.normal(9.0, 1.3, (B, nR)).astype(np.float32)
     return m, params, feat, y, mean.astype(np.float64), std.astype(np.float64)
 
 
+MU, SIGMA = -0.5, 0.3
+
+
 def test_param_roundtrip_and_count():
     m = lsp.Model(members=3, seed=1)
-    assert lsp.lsp_model_param_count() == R.N_PARAMS == 151561
+    assert lsp.lsp_model_param_count() == R.N_PARAMS == 149762
     assert m.members == 3
     p = np.random.default_rng(0).normal(0, 1, R.N_PARAMS).astype(np.float32)
     m.set_params(2, p)
@@ -58,7 +66,7 @@ def test_forward_matches_reference():
     m, params, feat, y, mean, std = _model_and_data()
     q = m.forward(torch.from_numpy(feat).cuda()).cpu().numpy()
     for e in range(2):
-        ref = R.forward(params[e].astype(np.float64), feat, mean, std, 9.0, 1.3, bf=True)["q"]
+        ref = R.forward(params[e].astype(np.float64), feat, mean, std, MU, SIGMA, bf=True)["q"]
         assert rel_l2(q[e], ref) <= 1e-3
         assert np.all(np.diff(q[e], axis=1) > 0)
     m.close()
@@ -67,7 +75,7 @@ def test_forward_matches_reference():
 def test_gradient_matches_reference():
     m, params, feat, y, mean, std = _model_and_data()
     g, loss = m.grad(1, torch.from_numpy(feat).cuda(), torch.from_numpy(y).cuda())
-    Lr, gr, _ = R.loss_and_grad(params[1].astype(np.float64), feat, y, mean, std, 9.0, 1.3, bf=True)
+    Lr, gr, _ = R.loss_and_grad(params[1].astype(np.float64), feat, y, mean, std, MU, SIGMA, bf=True)
     assert abs(loss.item() - Lr) <= 1e-4 * abs(Lr)
     gg = g.cpu().numpy()
     assert rel_l2(gg, gr) <= 1e-3
@@ -129,14 +137,18 @@ def test_fap_surrogate_and_fallback():
     feat = lsp.lsp_window_features(td, off, fm, df, nf)
     m = lsp.Model(members=3, seed=2)
     F = feat.cpu().numpy()
-    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, 8.0, 1.0)
+    mean, std = F.mean(0), F.std(0) + 1e-3
+    m.set_scalers(mean, std, 1e6, -0.4, 0.5)
     p_obs = torch.linspace(6.0, 12.0, 8).cuda()
     fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=10.0, mc_realizations=0)
-    q = m.forward(feat).cpu().numpy()
-    for b in range(8):
-        fe = [R.fap_from_quantiles(q[e, b], float(p_obs[b])) for e in range(3)]
-        assert abs(fap[b].item() - np.mean(fe)) <= 1e-5
-        assert abs(sig[b].item() - np.std(fe)) <= 1e-5
+    fe = []
+    for e in range(3):
+        raw = R.forward(m.get_params(e).astype(np.float64), F, mean.astype(np.float32).astype(np.float64),
+                        std.astype(np.float32).astype(np.float64), -0.4, 0.5, bf=True)["raw"]
+        fe.append(R.fap(raw, F, -0.4, 0.5, p_obs.cpu().numpy()))
+    fe = np.array(fe)
+    assert np.max(np.abs(fap.cpu().numpy() - fe.mean(0))) <= 1e-3
+    assert np.max(np.abs(sig.cpu().numpy() - fe.std(0))) <= 1e-3
     assert used.sum().item() == 0
     # forced fallback: every pattern answered by Monte Carlo with the same draws as lsp_mc_maxpower
     Rn = 256
@@ -148,6 +160,22 @@ def test_fap_surrogate_and_fallback():
     m.close()
 
 
+def test_reported_quantiles_and_fap_agree():
+    # one member: the FAP at its own tau-quantile is 1 - tau
+    t, off, fm, df, nf = _patterns(8, 6)
+    td = torch.from_numpy(t).cuda()
+    feat = lsp.lsp_window_features(td, off, fm, df, nf)
+    F = feat.cpu().numpy()
+    m = lsp.Model(members=1, seed=3)
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, -0.4, 0.5)
+    q = m.forward(feat)[0]
+    assert torch.all(q[:, 1:] > q[:, :-1])
+    for i, tau in enumerate(R.TAU):
+        fap, _, _ = m.fap(td, off, fm, df, nf, q[:, i].contiguous(), max_sigma=10.0, mc_realizations=0)
+        assert np.allclose(fap.cpu().numpy(), 1 - tau, atol=2e-5), tau
+    m.close()
+
+
 def test_short_training_reduces_loss():
     t, off, fm, df, nf = _patterns(64, 4)
     td = torch.from_numpy(t).cuda()
@@ -155,17 +183,18 @@ def test_short_training_reduces_loss():
     y = lsp.lsp_mc_maxpower(td, off, fm, df, nf, 64, seed=5)
     F = feat.cpu().numpy()
     Y = y.cpu().numpy()
+    nt, nfr = R.nt_nf(F)
+    W = R.w_of(Y, nt[:, None]) - np.log(nfr)[:, None]
     m = lsp.Model(members=1, seed=9)
-    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, float(Y.mean()), float(Y.std()))
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, float(W.mean()), float(W.std()))
     losses = []
     for step in range(300):
         _, loss = m.grad(0, feat, y, want_grad=False)
         m.adam_step(0, 3e-3)
         losses.append(loss.item())
-    # the per-pattern empirical quantiles minimize the in-sample pinball loss exactly: a floor
-    Ys = Y.astype(np.float64)
-    qf = np.stack([np.quantile(Ys, t, axis=1, method="inverted_cdf") for t in R.TAU], axis=1)
-    floor, _ = R.pinball(qf, Ys)
-    assert losses[-1] >= floor - 1e-6
+    # every pattern's own maximum-likelihood law bounds the in-sample loss from below
+    fits = [stats.gumbel_r.fit(W[b]) for b in range(W.shape[0])]
+    floor = np.mean([-np.mean(stats.gumbel_r.logpdf(W[b], *fits[b])) for b in range(W.shape[0])])
+    assert losses[-1] >= floor - 1e-4
     assert losses[-1] - floor < 0.5 * (losses[0] - floor)
     m.close()

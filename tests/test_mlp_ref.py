@@ -1,16 +1,27 @@
 """Pins of the CPU reference of the surrogate network (CPU only)."""
 import numpy as np
 import pytest
+from scipy import stats
 
+import oracle
 from oracle import mlp_ref as R
+
+
+def _feat(g, B):
+    """Random features with valid Nt (feat[64]) and Nf = 2 Nt (feat[67])."""
+    feat = g.normal(0, 1, (B, 68))
+    nt = np.rint(10 ** g.uniform(np.log10(200), np.log10(20000), B))
+    feat[:, 64] = np.log10(nt)
+    feat[:, 67] = np.log10(2 * nt)
+    return feat
 
 
 def _setup(seed=0, B=16, nR=40, scale=0.05):
     g = np.random.default_rng(seed)
     p = g.normal(0, scale, R.N_PARAMS)
-    feat = g.normal(0, 1, (B, 68))
+    feat = _feat(g, B)
     y = g.normal(9.0, 1.5, (B, nR))
-    return p, feat, y, np.zeros(68), np.ones(68), 9.0, 1.5
+    return p, feat, y, np.zeros(68), np.ones(68), -0.5, 0.3
 
 
 def test_bf16_rounding_known_values():
@@ -37,15 +48,43 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1e-3, abs(g).max()), i
 
 
-def test_pinball_closed_form():
-    # one pattern, samples 1..10: at q = 5.5 the tau-quantile loss is the mean of rho
-    y = np.arange(1.0, 11.0)[None, :]
-    q = np.full((1, 9), 5.5)
-    L, dq = R.pinball(q, y)
-    # L = 1/9 sum_tau mean_r rho_tau(y_r - q), written out sample by sample
-    expect = np.mean([np.mean([(v - 5.5) * (t - (v < 5.5)) for v in y[0]]) for t in R.TAU])
-    assert L == pytest.approx(expect, rel=1e-12)
-    assert np.allclose(dq, (0.5 - R.TAU[None, :]) / 9)
+def test_gumbel_nll_matches_library_and_vanishes_at_its_fit():
+    # the loss is the Gumbel (maximum) negative log-likelihood: scipy's density,
+    # and zero gradient at scipy's maximum-likelihood fit
+    w = stats.gumbel_r.rvs(loc=-0.4, scale=1.07, size=(1, 4000), random_state=5)
+    loc, scale = stats.gumbel_r.fit(w[0])
+    L, dm, db = R.gumbel_nll(np.array([loc]), np.array([scale]), w)
+    assert L == pytest.approx(-np.mean(stats.gumbel_r.logpdf(w[0], loc, scale)), rel=1e-12)
+    _, dm1, db1 = R.gumbel_nll(np.array([loc + 0.05]), np.array([scale * 1.05]), w)
+    assert abs(dm[0]) < 1e-3 * abs(dm1[0]) + 1e-9 and abs(db[0]) < 1e-3 * abs(db1[0]) + 1e-9
+
+
+def test_unit_law_is_eq3_with_all_frequencies_independent():
+    # m = 0, beta = 1: P(max >= p) = 1 - exp(-Nf e^-w) against Eq. (3),
+    # 1 - (1 - e^-w)^Nf; they differ by about (Nf e^-w)^2 / (2 Nf)
+    feat = _feat(np.random.default_rng(2), 8)
+    nt, nf = R.nt_nf(feat)
+    mu, sigma = 0.7, 1.3
+    raw = np.zeros((8, 2))
+    raw[:, 0] = -mu / sigma
+    for fap_target in (0.2, 0.05, 0.01, 0.001):
+        w = np.log(nf) - np.log(-np.log1p(-fap_target))
+        p = R.z_of(w, nt)
+        got = R.fap(raw, feat, mu, sigma, p)
+        eq3 = np.array([oracle.fap(float(p[i]), int(nt[i]), int(nf[i])) for i in range(8)])
+        lam = nf * np.exp(-w)
+        assert np.all(np.abs(got - eq3) <= lam ** 2 / nf), fap_target
+        assert np.allclose(got, fap_target, rtol=1e-12)
+
+
+def test_quantiles_hit_their_levels():
+    g = np.random.default_rng(4)
+    feat = _feat(g, 12)
+    raw = g.normal(0, 1.5, (12, 2))
+    q = R.quantiles(raw, feat, 0.3, 0.8)
+    assert np.all(np.diff(q, axis=1) > 0)
+    for i, t in enumerate(R.TAU):
+        assert np.allclose(R.fap(raw, feat, 0.3, 0.8, q[:, i]), 1 - t, rtol=1e-10)
 
 
 def test_adam_first_step_is_signed_lr():
@@ -55,20 +94,10 @@ def test_adam_first_step_is_signed_lr():
     assert np.allclose(w1, w - 0.01 * np.sign(g), atol=1e-9)
 
 
-def test_fap_interpolation_hits_the_levels():
-    q = np.array([5.0, 5.6, 6.3, 6.9, 7.4, 8.0, 8.5, 9.1, 9.6])
-    for i, t in enumerate(R.TAU):
-        assert R.fap_from_quantiles(q, q[i]) == pytest.approx(1 - t, rel=1e-12)
-    # monotone in p, and beyond the ends it follows the end segments
-    ps = np.linspace(3, 12, 50)
-    f = [R.fap_from_quantiles(q, p) for p in ps]
-    assert np.all(np.diff(f) < 0)
-
-
-def test_head_is_monotone_and_gelu_grad_matches():
-    raw = np.random.default_rng(3).normal(0, 3, (20, 9))
-    q = R.head(raw, 9.0, 1.5)
-    assert np.all(np.diff(q, axis=1) > 0)
+def test_head_scale_is_positive_and_gelu_grad_matches():
+    raw = np.random.default_rng(3).normal(0, 3, (20, 2))
+    m, b = R.head(raw, 9.0, 1.5)
+    assert np.all(b > 0) and np.allclose(R.head(np.zeros((1, 2)), 9.0, 1.5)[1], 1.0)
     z = np.linspace(-6, 6, 101)
     h = 1e-6
     assert np.allclose(R.gelu_grad(z), (R.gelu(z + h) - R.gelu(z - h)) / (2 * h), atol=1e-8)
