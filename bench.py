@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 METRIC = "Nt·Nf terms/s (split-FP32 vs plain) at max|ΔPn|≤1e-4; % FP32 VALU peak"
 FLOP_PER_TERM = 13          # phase mul/round/sub 3, sin+cos 2, four FMAs 8
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz, packed issue)
+# matrix-core form: per term, two complex products (XC + i XS and the
+# double-angle sum), each 4 real products in three FP16 passes: 24 multiply-adds
+MFMA_FLOP_PER_TERM = 48
+PEAK_FP16_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
 REL_TOL = 1e-4
 
 WORKLOADS = {
@@ -44,8 +48,9 @@ def make_curve(name):
     return {"c0": synth.c0, "c1": synth.c1, "c2": synth.c2, "paper": synth.paper_standin}[name]()
 
 
-def kernel_source_hash():
-    p = os.path.join(ROOT, "paper_1007_1658_amd", "csrc", "pgram_kernels.hip")
+def kernel_source_hash(kernel_name=""):
+    name = "pgram_mfma.hip" if "mfma" in kernel_name else "pgram_kernels.hip"
+    p = os.path.join(ROOT, "paper_1007_1658_amd", "csrc", name)
     with open(p, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
@@ -60,7 +65,7 @@ def traffic_from_profiles(kernel_name, workload):
         with open(p) as f:
             d = json.load(f)
         e = d.get(f"{kernel_name}|{workload}")
-        if not e or e.get("source_sha") != kernel_source_hash():
+        if not e or e.get("source_sha") != kernel_source_hash(kernel_name):
             return None
         return float(e["bytes_per_launch"])
     except Exception:
@@ -281,7 +286,10 @@ def main():
         plain = {"value": terms / sec_p, "ms_per_step": sec_p * 1e3, "max_rel_err": err_plain,
                  "meets_1e-4": bool(err_plain <= REL_TOL)}
 
-    achieved = FLOP_PER_TERM * terms / k_avg_s / 1e12
+    mfma = "mfma" in k_name
+    flop = MFMA_FLOP_PER_TERM if mfma else FLOP_PER_TERM
+    peak = PEAK_FP16_TFLOPS if mfma else PEAK_FP32_TFLOPS
+    achieved = flop * terms / k_avg_s / 1e12
     traffic = traffic_from_profiles(k_name, args.config)
     line = {
         "metric": METRIC,
@@ -302,15 +310,17 @@ def main():
         "meets_1e-4": bool(err_split <= REL_TOL),
         "plain": plain,
         "roofline": {
-            "bound": "alu",
+            "bound": "mfma" if mfma else "alu",
             "achieved": achieved,
-            "peak": PEAK_FP32_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_TFLOPS,
+            "frac": achieved / peak,
             "traffic": traffic,
             "kernel": k_name,
             "kernel_avg_ms": k_avg_s * 1e3,
-            "flop_per_term": FLOP_PER_TERM,
+            "flop_per_term": flop,
+            # the same kernel time priced as the FP32-vector form's 13 FLOP per term
+            "fp32_valu_equiv_frac": FLOP_PER_TERM * terms / k_avg_s / 1e12 / PEAK_FP32_TFLOPS,
         },
         "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
     }

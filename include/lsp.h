@@ -74,7 +74,14 @@ typedef enum lsp_trig_mode {
        sample), the rest by the three-term recurrence
        c_{m+1} = 2 cos(step) c_m - c_{m-1} (and likewise for sin).  Re-seeded
        exactly at every sample.  Only with LSP_PHASE_SPLIT / SPLIT32. */
-    LSP_TRIG_RECUR = 2
+    LSP_TRIG_RECUR = 2,
+    /* Matrix cores: with k = 64a + b, the sums of Eq. (8) are the complex
+       products sum_j [x_j e^{i w_a t'_j}] [e^{i b dw t'_j}] (and the same at
+       twice the angle for CC, CS), FP16 hi/lo operands in three passes with
+       FP32 accumulation (v_mfma_f32_32x32x16_f16); one sin/cos pair per
+       (a, j) and per (b, j).  Only with LSP_PHASE_SPLIT; m = 32 (a wave
+       covers 32 a-rows x 64 b = 2048 frequencies), unroll 1, sum TWO. */
+    LSP_TRIG_MFMA = 3
 } lsp_trig_mode;
 
 /* How each lane's FP32 partial sums (kept over groups of 256 samples) are
@@ -89,7 +96,7 @@ typedef enum lsp_sum_mode {
    (tuner cache, else heuristic).  lsp_autotune lists what is built. */
 typedef struct lsp_tile {
     int32_t trig;   /* lsp_trig_mode */
-    int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4..24 */
+    int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4..24; MFMA 32 */
     int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2 or 4 */
     int32_t splits; /* workgroups sharing one frequency block along the sample
                        axis (1 = none); partials merged in fixed order in FP64 */

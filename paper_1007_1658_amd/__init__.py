@@ -32,9 +32,10 @@ LSP_PHASE_SPLIT32 = 2
 LSP_TRIG_AUTO = 0
 LSP_TRIG_DIRECT = 1
 LSP_TRIG_RECUR = 2
+LSP_TRIG_MFMA = 3
 
 PHASES = {"split": LSP_PHASE_SPLIT, "naive": LSP_PHASE_NAIVE, "split32": LSP_PHASE_SPLIT32}
-TRIGS = {"auto": LSP_TRIG_AUTO, "direct": LSP_TRIG_DIRECT, "recur": LSP_TRIG_RECUR}
+TRIGS = {"auto": LSP_TRIG_AUTO, "direct": LSP_TRIG_DIRECT, "recur": LSP_TRIG_RECUR, "mfma": LSP_TRIG_MFMA}
 
 
 class LspError(RuntimeError):

@@ -126,6 +126,9 @@ void pgram_complete_tile(int phase, lsp_tile &tile);
 int pgram_list_tiles(int phase, lsp_tile *out, int cap);
 hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu);
 
+// the matrix-core form of the main kernel (pgram_mfma.hip); 32 a-rows x 64 b per wave
+__global__ void pgram_mfma_kernel(PgramArgs a);
+
 // ---- batched launchers (batch_kernels.hip) ---------------------------------------
 hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,
                           hipStream_t s);

@@ -262,7 +262,9 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
         }
         const lsp_tile d = default_tile(phase, Nt, Nf, di->cus);
         if (tile.trig == 0) tile.trig = d.trig;
-        if (tile.m == 0) tile.m = (tile.trig == d.trig) ? d.m : (tile.trig == LSP_TRIG_DIRECT ? 1 : 8);
+        if (tile.m == 0)
+            tile.m = (tile.trig == d.trig) ? d.m
+                                           : (tile.trig == LSP_TRIG_DIRECT ? 1 : (tile.trig == LSP_TRIG_MFMA ? 32 : 8));
         if (tile.waves == 0) tile.waves = d.waves;
         if (tile.sum == 0 && tile.trig == d.trig && tile.m == d.m) tile.sum = d.sum;
         pgram_complete_tile(phase, tile);
@@ -739,7 +741,8 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, doubl
         g_last_error = "unknown phase mode";
         return LSP_ERR_INVALID_ARG;
     }
-    if (o.tile.trig != 0 && o.tile.trig != LSP_TRIG_DIRECT && o.tile.trig != LSP_TRIG_RECUR) {
+    if (o.tile.trig != 0 && o.tile.trig != LSP_TRIG_DIRECT && o.tile.trig != LSP_TRIG_RECUR &&
+        o.tile.trig != LSP_TRIG_MFMA) {
         g_last_error = "unknown trig mode";
         return LSP_ERR_INVALID_ARG;
     }
@@ -749,6 +752,10 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, doubl
     }
     if (o.phase == LSP_PHASE_NAIVE && o.tile.trig == LSP_TRIG_RECUR) {
         g_last_error = "the recurrence needs the split phase";
+        return LSP_ERR_UNSUPPORTED;
+    }
+    if (o.phase != LSP_PHASE_SPLIT && o.tile.trig == LSP_TRIG_MFMA) {
+        g_last_error = "the matrix-core form needs the split phase";
         return LSP_ERR_UNSUPPORTED;
     }
     hipStream_t s = (hipStream_t)stream;

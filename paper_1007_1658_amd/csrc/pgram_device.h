@@ -11,7 +11,7 @@
 namespace lsp {
 
 enum { PH_SPLIT = LSP_PHASE_SPLIT, PH_NAIVE = LSP_PHASE_NAIVE, PH_SPLIT32 = LSP_PHASE_SPLIT32 };
-enum { TR_DIRECT = LSP_TRIG_DIRECT, TR_RECUR = LSP_TRIG_RECUR };
+enum { TR_DIRECT = LSP_TRIG_DIRECT, TR_RECUR = LSP_TRIG_RECUR, TR_MFMA = LSP_TRIG_MFMA };
 
 // hardware sin/cos take their argument in revolutions: sin_rev(r) = sin(2 pi r)
 __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }

@@ -159,6 +159,8 @@ static const Variant kVariants[] = {
     // all-FP32 split phase
     LSP_V(PH_SPLIT32, TR_RECUR, 8, 4, SUM_KAHAN), LSP_V(PH_SPLIT32, TR_RECUR, 16, 2, SUM_KAHAN),
     LSP_V(PH_SPLIT32, TR_DIRECT, 1, 4, SUM_KAHAN), LSP_V(PH_SPLIT32, TR_DIRECT, 4, 4, SUM_KAHAN),
+    // split phase on the matrix cores (per-chunk FP32 accumulation)
+    {PH_SPLIT, TR_MFMA, 32, 1, SUM_TWO, pgram_mfma_kernel, "pgram_mfma_kernel<PH_SPLIT,TR_MFMA,32,1,SUM_TWO>"},
     // the paper's FP32 arithmetic (two-level sums, as its chunked totals)
     LSP_V(PH_NAIVE, TR_DIRECT, 1, 4, SUM_TWO),    LSP_V(PH_NAIVE, TR_DIRECT, 2, 4, SUM_TWO),
     LSP_V(PH_NAIVE, TR_DIRECT, 4, 4, SUM_TWO),

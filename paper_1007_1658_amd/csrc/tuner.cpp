@@ -116,11 +116,12 @@ lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream, lsp
         std::vector<lsp_tile> built((size_t)nv);
         pgram_list_tiles(phase, built.data(), nv);
         // the split phases keep their compensated sums: two-level variants are
-        // reachable by explicit request only
+        // reachable by explicit request only (the matrix-core form, whose sums
+        // are the FP32 accumulators of its products, is a candidate)
         const int want_sum = (phase == LSP_PHASE_NAIVE) ? LSP_SUM_TWO : LSP_SUM_KAHAN;
         for (lsp_tile t : built)
             for (int w : {2, 4}) {
-                if (t.sum != want_sum) continue;
+                if (t.sum != want_sum && t.trig != LSP_TRIG_MFMA) continue;
                 t.waves = w;
                 int per_cu = 0;
                 t.splits = 1;

@@ -18,7 +18,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 
 import paper_1007_1658_amd as lsp  # noqa: E402
 
-TRIG_NAME = {lsp.LSP_TRIG_DIRECT: "direct", lsp.LSP_TRIG_RECUR: "recur"}
+TRIG_NAME = {lsp.LSP_TRIG_DIRECT: "direct", lsp.LSP_TRIG_RECUR: "recur", lsp.LSP_TRIG_MFMA: "mfma"}
 SUM_NAME = {lsp.LSP_SUM_KAHAN: "kahan", lsp.LSP_SUM_TWO: "two"}
 
 # every launch shape built into the library, per phase mode
@@ -52,7 +52,7 @@ def test_c0_all_shapes(c0_case, phase, trig, m, unroll, summ, waves, splits):
 ])
 @pytest.mark.parametrize("phase,trig,m", [("split", "recur", 8), ("split", "recur", 16), ("split", "recur", 14),
                                           ("split", "direct", 1), ("split32", "recur", 8),
-                                          ("naive", "direct", 4)])
+                                          ("naive", "direct", 4), ("split", "mfma", 32)])
 def test_ragged_sizes(Nt, Nf, splits, phase, trig, m):
     print(f"ragged Nt={Nt} Nf={Nf} splits={splits} {phase}/{trig}/{m}", flush=True)
     g = np.random.default_rng([11, Nt, Nf])
@@ -118,6 +118,46 @@ def test_c2_precision_split_vs_naive():
     print(f"c2 sampled rel err split {err_s:.3e} naive {err_n:.3e}", flush=True)
     assert err_s <= REL_TOL
     assert err_n > 10 * err_s
+
+
+@pytest.mark.parametrize("config", ["c1", "c2"])
+@pytest.mark.parametrize("waves", [4, 2])
+def test_matrix_core_form_full_size_sampled(config, waves):
+    """The matrix-core form at full size (c1: small amplitudes; c2: epoch-offset
+    times), oracle on sampled bins and around the peak."""
+    c = getattr(synth, config)()
+    t, x = to_dev(c)
+    print(f"{config} mfma waves={waves} Nt={c.Nt} Nf={c.Nf}", flush=True)
+    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, c.Nf, trig="mfma", m=32, waves=waves).cpu().numpy()
+    g = np.random.default_rng(3)
+    kpk = int(np.argmax(Pg))
+    k = np.unique(np.concatenate([g.integers(0, c.Nf, 400), np.arange(max(0, kpk - 8), min(c.Nf, kpk + 9)),
+                                  np.arange(0, 64), np.arange(c.Nf - 64, c.Nf)]))
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, k=k)
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
+    print(f"{config} mfma sampled rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert int(k[np.argmax(P)]) == kpk or abs(P.max() - P[np.searchsorted(k, kpk)]) <= REL_TOL * P.max()
+
+
+def test_matrix_core_form_outlier_and_dynamic_range():
+    """A 1000-sigma spike among unit noise, and a 1e-6 sinusoid in 1e-7 noise:
+    the per-chunk power-of-two scaling keeps both within the bar."""
+    g = np.random.default_rng(17)
+    Nt, Nf = 3000, 6000
+    tt = np.sort(g.uniform(0, 50, Nt))
+    df = 1.0 / (4 * (tt[-1] - tt[0]))
+    spike = g.normal(0, 1, Nt)
+    spike[1234] = 1000.0
+    tiny = 1e-6 * np.sin(2 * np.pi * 2.2 * tt) + 1e-7 * g.normal(0, 1, Nt)
+    for xx in (spike, tiny):
+        c = synth.Curve(tt, xx.astype(np.float32), df, df, Nf)
+        P = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=Nf)
+        t, x = to_dev(c)
+        for splits in (1, 7):
+            Pg = lsp.lsp_periodogram_ex(t, x, df, df, Nf, trig="mfma", m=32, waves=4, splits=splits).cpu().numpy()
+            assert rel_err(Pg, P) <= REL_TOL
+            assert peak_matches(Pg, P)
 
 
 def test_deterministic_rerun():
