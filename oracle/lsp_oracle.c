@@ -307,6 +307,115 @@ int oracle_window(const double *t, int64_t Nt, double f_min, double df,
     return ORACLE_OK;
 }
 
+/* ---- generalized (floating-mean, weighted) periodogram ------------------
+
+   Section 6.3 names the generalization of Zechmeister & Kuerster (2009,
+   A&A 496, 577): the mean is fitted at every frequency instead of being
+   removed beforehand, and samples may carry weights.  Its definition is a
+   weighted least-squares fit y_j ~ a cos wt_j + b sin wt_j + c with weights
+   w_j; the power is the fraction of the weighted variance of y that the
+   sinusoid explains,
+       p(w) = 1 - chi2_min(w) / chi2_0,   chi2_0 = sum w_j (y_j - Y)^2,
+   Y the weighted mean.  Eliminating c centres the basis and the data:
+   with normalized weights (sum w = 1), C = sum w cos, S = sum w sin,
+       YC = sum w (y - Y) cos,   YS = sum w (y - Y) sin,
+       CC = sum w cos^2 - C^2,   SS = sum w sin^2 - S^2,   CS = sum w cos sin - C S,
+   the explained part is [YC YS] G^{-1} [YC YS]^T with G = [[CC, CS], [CS, SS]],
+   so p = (SS YC^2 + CC YS^2 - 2 CS YC YS) / (YY (CC SS - CS^2)), YY = chi2_0.
+   The 2x2 system is solved as written; a frequency whose Gram determinant is
+   <= 1e-12 (cos and sin collinear with the constant: f = 0) falls back to the
+   one-dimensional fit on whichever of cos, sin is not degenerate, else 0.
+   w NULL: equal weights.  Same grid and phase conventions as above. */
+
+static double gls_one_frequency(const double *t, const double *yc, const double *w,
+                                int64_t Nt, double YY, double f)
+{
+    nsum C = {0, 0}, S = {0, 0}, YCs = {0, 0}, YSs = {0, 0}, CCs = {0, 0}, SSs = {0, 0}, CSs = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        double p = f * t[j];
+        double phi = p - nearbyint(p);
+        double c = cos(TWO_PI * phi), s = sin(TWO_PI * phi);
+        nsum_add(&C, w[j] * c);
+        nsum_add(&S, w[j] * s);
+        nsum_add(&YCs, w[j] * yc[j] * c);
+        nsum_add(&YSs, w[j] * yc[j] * s);
+        nsum_add(&CCs, w[j] * c * c);
+        nsum_add(&SSs, w[j] * s * s);
+        nsum_add(&CSs, w[j] * c * s);
+    }
+    double Cv = nsum_get(&C), Sv = nsum_get(&S);
+    double YC = nsum_get(&YCs), YS = nsum_get(&YSs);
+    double CC = nsum_get(&CCs) - Cv * Cv;
+    double SS = nsum_get(&SSs) - Sv * Sv;
+    double CS = nsum_get(&CSs) - Cv * Sv;
+    double D = CC * SS - CS * CS;
+    if (D > 1e-12)
+        return (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
+    if (CC > 1e-12)
+        return YC * YC / (YY * CC);
+    if (SS > 1e-12)
+        return YS * YS / (YY * SS);
+    return 0.0;
+}
+
+int oracle_gls(const double *t, const double *y, const double *w_in, int64_t Nt,
+               double f_min, double df, const int64_t *klist, int64_t n_out,
+               double *p, int nthreads)
+{
+    if (!t || !y || !p || Nt < 3 || n_out < 0 || !isfinite(f_min) || !isfinite(df))
+        return ORACLE_ERR_ARG;
+    double *w = (double *)malloc((size_t)Nt * sizeof(double));
+    double *yc = (double *)malloc((size_t)Nt * sizeof(double));
+    if (!w || !yc) {
+        free(w);
+        free(yc);
+        return ORACLE_ERR_ARG;
+    }
+    nsum W = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        w[j] = w_in ? w_in[j] : 1.0;
+        if (!(w[j] >= 0.0) || !isfinite(w[j])) {
+            free(w);
+            free(yc);
+            return ORACLE_ERR_ARG;
+        }
+        nsum_add(&W, w[j]);
+    }
+    double Wt = nsum_get(&W);
+    if (!(Wt > 0.0)) {
+        free(w);
+        free(yc);
+        return ORACLE_ERR_ARG;
+    }
+    nsum Ys = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        w[j] /= Wt;
+        nsum_add(&Ys, w[j] * y[j]);
+    }
+    double Y = nsum_get(&Ys);
+    nsum V = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        yc[j] = y[j] - Y;
+        nsum_add(&V, w[j] * yc[j] * yc[j]);
+    }
+    double YY = nsum_get(&V);
+    if (!(YY > 0.0)) {
+        free(w);
+        free(yc);
+        return ORACLE_ERR_ZERO_VARIANCE;
+    }
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads)
+    for (int64_t i = 0; i < n_out; ++i) {
+        int64_t k = klist ? klist[i] : i;
+        p[i] = gls_one_frequency(t, yc, w, Nt, YY, f_min + (double)k * df);
+    }
+    free(w);
+    free(yc);
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---- counter-based normal deviates (white-noise Monte Carlo) -------------
