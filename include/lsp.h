@@ -138,6 +138,31 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt,
                               double f_min, double df, int64_t Nf, float *Pn,
                               void *stream, const lsp_options *opt);
 
+/* ---- generalized (floating-mean, weighted) periodogram -------------------------
+
+   Section 6.3 points to the generalization of Zechmeister & Kuerster (2009):
+   at every frequency the weighted least-squares fit y ~ a cos wt + b sin wt + c
+   (the mean is fitted, not removed beforehand), and the power is the fraction
+   of the weighted variance of y it explains,
+     p = (SS YC^2 + CC YS^2 - 2 CS YC YS) / (YY (CC SS - CS^2)),
+   with normalized weights (sum 1), Y = sum w y, YY = sum w (y - Y)^2,
+   C = sum w cos, S = sum w sin, YC = sum w (y - Y) cos, YS likewise,
+   CC = sum w cos^2 - C^2, SS = sum w sin^2 - S^2, CS = sum w cos sin - C S.
+   A degenerate direction (CC or SS <= 1e-5, or CC SS - CS^2 <= 1e-10: f
+   near 0, where the FP32 sums cannot resolve them) falls back to the
+   one-dimensional fit on the other, else p = 0.  0 <= p <= 1.  Computed on
+   the matrix cores (LSP_TRIG_MFMA form with a third complex sum), split phase.
+
+   t  device FP64 [Nt], y device FP32 [Nt], w device FP32 [Nt] weights >= 0
+   (e.g. 1/sigma^2) or NULL for equal weights; Nt >= 3; grid as above;
+   p device FP32 [Nf] output, fully written.  waves: 0 (library's choice),
+   1, 2 or 4 per workgroup; splits: 0 (library's choice) or the number of
+   chunks of the sample axis.  All weights zero or a constant y give p = 0.
+   Asynchronous on stream.  Errors: LSP_ERR_INVALID_ARG as above. */
+lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
+                   double f_min, double df, int64_t Nf, float *p, int32_t waves,
+                   int32_t splits, void *stream);
+
 /* ---- many light curves in one persistent launch ------------------------------
 
    Curve c owns samples [off[c], off[c+1]) of t and x and its own grid

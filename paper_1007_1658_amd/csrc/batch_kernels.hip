@@ -149,6 +149,7 @@ __global__ void __launch_bounds__(256) batch_value_kernel(BatchArgs a)
     s.t_ref = a.t_ref[3 * cv.group];
     s.t_min = a.t_ref[3 * cv.group + 1];
     s.t_max = a.t_ref[3 * cv.group + 2];
+    s.wsum = (double)cv.Nt;
     s.pad_ = 0;
     if (threadIdx.x == 0) a.stats[c] = s;
     for (int64_t j = threadIdx.x; j < cv.Nt; j += 256)

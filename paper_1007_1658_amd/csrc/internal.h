@@ -23,6 +23,7 @@ struct CurveStats {
     double inv_var;  // 1/var, 0 when var == 0
     double t_ref;    // time origin removed from t (0 in NAIVE mode)
     double t_min, t_max;
+    double wsum;     // sum of the weights (Nt when unweighted)
     int32_t zero_var;
     int32_t pad_;
 };
@@ -40,6 +41,7 @@ struct Records {
     float *xv;  // x - mean
     float *rc;  // cos(2 pi * 64 df * t')  (step of the frequency recurrence)
     float *rs;  // sin(2 pi * 64 df * t')
+    float *wv;  // generalized periodogram: normalized weight w_j / sum w (else unused)
 };
 
 struct PgramArgs {
@@ -128,6 +130,12 @@ hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu);
 
 // the matrix-core form of the main kernel (pgram_mfma.hip); 32 a-rows x 64 b per wave
 __global__ void pgram_mfma_kernel(PgramArgs a);
+// the generalized periodogram (pgram_mfma.hip): weighted prep, matrix-core sums
+// (32 a-rows x 32 b per wave, six sums into part[splits][6][Nf]) and FP64 merge
+hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
+                                int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s);
+hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+constexpr int kGlsFreqPerWave = 32 * 32;
 
 // ---- batched launchers (batch_kernels.hip) ---------------------------------------
 hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,

@@ -295,6 +295,7 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     rec.xv = (float *)(base + L.xv);
     rec.rc = (float *)(base + L.rc);
     rec.rs = (float *)(base + L.rs);
+    rec.wv = nullptr;
     CurveStats *stats = (CurveStats *)(base + L.stats);
     hipError_t e = launch_prep(t, x, Nt, (double)kWave * df, phase, (Moments *)(base + L.moments), n_mom,
                                stats, rec, s);
@@ -767,6 +768,83 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, doubl
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "status read-back");
     return h.zero_var ? LSP_ERR_ZERO_VARIANCE : LSP_OK;
+}
+
+lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, double f_min, double df,
+                   int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream)
+{
+    if (!t || !y || !p || Nt < 3 || Nt > kMaxNt || Nf < 1 || Nf > kMaxNf || !finite_nonneg(f_min) ||
+        !finite_pos(df) || !std::isfinite(f_min + (double)(Nf - 1) * df)) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4) {
+        g_last_error = "waves must be 0 (library's choice), 1, 2 or 4";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (splits < 0) {
+        g_last_error = "negative split count";
+        return LSP_ERR_INVALID_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    lsp_status st = device_info(&dev, &di);
+    if (st != LSP_OK) return st;
+    if (waves == 0) waves = 4;
+    if (splits == 0) splits = heuristic_splits(Nt, Nf, kGlsFreqPerWave / kWave, di->cus, waves, 2);
+    int64_t chunk = 0;
+    int eff = 1;
+    split_geometry(Nt, splits, &chunk, &eff);
+
+    // workspace: stats, moments, th, tl, xv, wv, six partial sums per chunk
+    const int n_mom = moment_blocks(Nt);
+    size_t o = 0;
+    const size_t o_stats = o;
+    o = align_up(o + sizeof(CurveStats));
+    const size_t o_mom = o;
+    o = align_up(o + sizeof(Moments) * (size_t)n_mom);
+    const size_t fb = align_up(sizeof(float) * (size_t)Nt);
+    const size_t o_th = o, o_tl = o + fb, o_xv = o + 2 * fb, o_wv = o + 3 * fb;
+    o += 4 * fb;
+    const size_t o_part = o;
+    o = align_up(o + sizeof(float) * 6 * (size_t)Nf * (size_t)eff);
+    StreamCtx &sc = stream_ctx(dev, s);
+    st = ensure(sc.ws, o, s);
+    if (st != LSP_OK) return st;
+    char *base = (char *)sc.ws.ptr;
+    Records rec;
+    rec.th = (float *)(base + o_th);
+    rec.tl = (float *)(base + o_tl);
+    rec.xv = (float *)(base + o_xv);
+    rec.wv = (float *)(base + o_wv);
+    rec.rc = nullptr;
+    rec.rs = nullptr;
+    CurveStats *stats = (CurveStats *)(base + o_stats);
+    hipError_t e = launch_prep_weighted(t, y, w, Nt, (Moments *)(base + o_mom), n_mom, stats, rec, s);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+    PgramArgs a;
+    a.rec = rec;
+    a.stats = stats;
+    a.Nt = Nt;
+    a.chunk = chunk;
+    a.f_min = f_min;
+    a.df = df;
+    a.Nf = Nf;
+    a.Pn = p;
+    a.part = (float *)(base + o_part);
+    a.splits = eff;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (ctx().prof) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return hip_fail(hipGetLastError(), "hipEventCreate");
+        ctx().prof_events.emplace_back(ev0, ev1);
+        ctx().prof_name = "gls_mfma_kernel";
+    }
+    e = launch_gls(a, waves, s, ev0, ev1);
+    if (e != hipSuccess) return hip_fail(e, "generalized periodogram launch");
+    return LSP_OK;
 }
 
 lsp_status lsp_periodogram(const double *t, const float *x, int64_t Nt, double f_min, double df,

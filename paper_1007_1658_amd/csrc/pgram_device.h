@@ -42,6 +42,18 @@ __device__ __forceinline__ void moments_push(Moments &a, double x, double t)
     a.tmax = fmax(a.tmax, t);
 }
 
+// one sample with weight w >= 0 (West's weighted update; n is the weight sum)
+__device__ __forceinline__ void moments_push_w(Moments &a, double x, double w, double t)
+{
+    a.tmin = fmin(a.tmin, t);
+    a.tmax = fmax(a.tmax, t);
+    if (!(w > 0.0)) return;
+    a.n += w;
+    double d = x - a.mean;
+    a.mean += d * (w / a.n);
+    a.m2 += w * d * (x - a.mean);
+}
+
 // Chan, Golub & LeVeque pairwise combination
 __device__ __forceinline__ Moments moments_merge(const Moments &a, const Moments &b)
 {

@@ -52,6 +52,7 @@ __global__ void __launch_bounds__(256) prep_finalize_kernel(const Moments *__res
         s.inv_var = s.zero_var ? 0.0 : 1.0 / s.var;
         s.t_min = m.tmin;
         s.t_max = m.tmax;
+        s.wsum = m.n;
         s.t_ref = (phase == PH_NAIVE) ? 0.0 : 0.5 * (m.tmin + m.tmax);
         s.pad_ = 0;
         *st = s;
@@ -79,6 +80,51 @@ hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_
     int64_t nb = (Nt + 255) / 256;
     hipLaunchKernelGGL(prep_records_kernel, dim3((unsigned)nb), dim3(256), 0, s, t, x, Nt,
                        (const CurveStats *)stats, step_df, phase, rec);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Prep of the generalized periodogram: weighted moments (weights w_j >= 0,
+// NULL = all 1), then records t' (split), w_j (y_j - Y) / W and w_j / W.
+
+__global__ void __launch_bounds__(256) prep_moments_w_kernel(const double *__restrict__ t,
+                                                             const float *__restrict__ y,
+                                                             const float *__restrict__ w, int64_t Nt,
+                                                             Moments *__restrict__ out)
+{
+    Moments m = moments_empty();
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < Nt; j += stride)
+        moments_push_w(m, (double)y[j], w ? (double)w[j] : 1.0, t[j]);
+    m = block_merge_256(m);
+    if (threadIdx.x == 0) out[blockIdx.x] = m;
+}
+
+__global__ void __launch_bounds__(256) prep_records_w_kernel(const double *__restrict__ t,
+                                                             const float *__restrict__ y,
+                                                             const float *__restrict__ w, int64_t Nt,
+                                                             const CurveStats *__restrict__ st, Records rec)
+{
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= Nt) return;
+    const CurveStats s = *st;
+    const double tp = t[j] - s.t_ref;
+    const float th = (float)tp;
+    rec.th[j] = th;
+    rec.tl[j] = (float)(tp - (double)th);
+    const double wn = (s.wsum > 0.0) ? (w ? (double)w[j] : 1.0) / s.wsum : 0.0;
+    rec.xv[j] = (float)(wn * ((double)y[j] - s.mean));
+    rec.wv[j] = (float)wn;
+}
+
+hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
+                                int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(prep_moments_w_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, y, w, Nt, moments);
+    hipLaunchKernelGGL(prep_finalize_kernel, dim3(1), dim3(256), 0, s, (const Moments *)moments,
+                       n_moment_blocks, (int)PH_SPLIT, stats);
+    hipLaunchKernelGGL(prep_records_w_kernel, dim3((unsigned)((Nt + 255) / 256)), dim3(256), 0, s, t, y, w, Nt,
+                       (const CurveStats *)stats, rec);
     return hipGetLastError();
 }
 

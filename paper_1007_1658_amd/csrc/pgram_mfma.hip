@@ -20,9 +20,15 @@
 // Phases are FP64 products reduced to revolutions (as the SPLIT mode).
 //
 // Work split: a workgroup of W waves owns a-rows [32 W blockIdx.x, +32 W) and
-// all 64 b; wave w owns 32 a-rows (one 32 x 64 output tile per sum).  Per
+// all b; wave w owns 32 a-rows (one 32 x 64 output tile per sum).  Per
 // block of 32 samples the workgroup writes the R operands once to LDS (shared
 // by its waves); each lane builds its own L operands in registers.
+//
+// The same products give the generalized (floating-mean, weighted)
+// periodogram named in Section 6.3 (Zechmeister & Kuerster 2009): with
+// normalized weights w_j and weighted-centred values, a third complex sum
+// sum_j w_j e^{i w t'_j} supplies C and S, and the double-angle sum is
+// weighted (b range 32 there, k = 32a + b, to keep six accumulators).
 #include "pgram_device.h"
 
 namespace lsp {
@@ -36,11 +42,13 @@ constexpr float kTrigScale = 16384.0f;  // 2^14
 
 enum { RR_H = 0, RR_L, RI_H, RI_L, R2R_H, R2R_L, R2I_H, R2I_L, R_KINDS };
 
+template <int NB, bool GLS>
 struct MfmaLds {
     double t[kMB];
     float x[kMB];
-    float red[kMaxWaves];
-    _Float16 R[R_KINDS][64][kMRow];
+    float w[GLS ? kMB : 1];
+    float red[2][kMaxWaves];
+    _Float16 R[R_KINDS][32 * NB][kMRow];
 };
 
 __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
@@ -55,11 +63,46 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// the complex operand v = (re, im) as hi/lo FP16 halves, plus -im for the real part
+struct COp {
+    halfx8 rh, rl, ih, il, nih, nil;
+    __device__ __forceinline__ void set(int i, float re, float im)
+    {
+        _Float16 h, l;
+        split16(re, h, l);
+        rh[i] = h;
+        rl[i] = l;
+        split16(im, h, l);
+        ih[i] = h;
+        il[i] = l;
+        nih[i] = -h;
+        nil[i] = -l;
+    }
+};
+
 #define LSP_MFMA(A, B, C) C = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, C, 0, 0, 0)
 
-__global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
+// accR += Re(L R), accI += Im(L R), three FP16 passes each
+#define LSP_CMAC(L, BRH, BRL, BIH, BIL, ACCR, ACCI)                             \
+    do {                                                                       \
+        LSP_MFMA(L.rh, BRH, ACCR); LSP_MFMA(L.rh, BIH, ACCI);                  \
+        LSP_MFMA(L.rh, BRL, ACCR); LSP_MFMA(L.rh, BIL, ACCI);                  \
+        LSP_MFMA(L.rl, BRH, ACCR); LSP_MFMA(L.rl, BIH, ACCI);                  \
+        LSP_MFMA(L.nih, BIH, ACCR); LSP_MFMA(L.ih, BRH, ACCI);                 \
+        LSP_MFMA(L.nih, BIL, ACCR); LSP_MFMA(L.ih, BRL, ACCI);                 \
+        LSP_MFMA(L.nil, BIH, ACCR); LSP_MFMA(L.il, BRH, ACCI);                 \
+    } while (0)
+
+// NB: 32-wide b subtiles per wave (b range 32 NB, k = 32 NB a + b).
+// GLS = false: sums XC + i XS and sum e^{2i wt}; slots [XC, XS, CC, CS].
+// GLS = true:  sums YC + i YS, C + i S and sum w e^{2i wt};
+//              slots [C, S, YC, YS, Re/2, Im/2] (weights normalized to 1).
+template <int NB, bool GLS>
+__device__ __forceinline__ void mfma_sums(const PgramArgs &a)
 {
-    __shared__ MfmaLds S;
+    constexpr int BW = 32 * NB;
+    constexpr int NACC = GLS ? 6 : 4;
+    __shared__ MfmaLds<NB, GLS> S;
     const int tid = threadIdx.x;
     const int nw = blockDim.x / kWave;  // waves in the workgroup (1, 2 or 4)
     const int lane = tid & (kWave - 1);
@@ -70,38 +113,52 @@ __global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
     const int64_t jb = (int64_t)split * a.chunk;
     const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
 
-    // value scale for this chunk: 2^(14 - e) with max|x - mean| < 2^e
-    float mx = 0.f;
-    for (int64_t j = jb + tid; j < je; j += blockDim.x) mx = fmaxf(mx, fabsf(a.rec.xv[j]));
+    // chunk scales: 2^(14 - e) with max|value| < 2^e (values; GLS: also weights)
+    float mx = 0.f, mw = 0.f;
+    for (int64_t j = jb + tid; j < je; j += blockDim.x) {
+        mx = fmaxf(mx, fabsf(a.rec.xv[j]));
+        if (GLS) mw = fmaxf(mw, a.rec.wv[j]);
+    }
     mx = wave_max(mx);
-    if (lane == 0) S.red[wave] = mx;
+    if (GLS) mw = wave_max(mw);
+    if (lane == 0) {
+        S.red[0][wave] = mx;
+        S.red[1][wave] = mw;
+    }
     __syncthreads();
-    mx = S.red[0];
-    for (int w = 1; w < nw; ++w) mx = fmaxf(mx, S.red[w]);
-    int ex = 0;
+    mx = S.red[0][0];
+    mw = S.red[1][0];
+    for (int w = 1; w < nw; ++w) {
+        mx = fmaxf(mx, S.red[0][w]);
+        mw = fmaxf(mw, S.red[1][w]);
+    }
+    int ex = 0, ew = 0;
     (void)frexpf(mx, &ex);  // mx = m 2^ex, 0.5 <= m < 1 (ex = 0 for mx = 0)
+    (void)frexpf(mw, &ew);
     const float xscale = ldexpf(1.0f, 14 - ex);
+    const float wscale = ldexpf(1.0f, 14 - ew);
 
     const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
-    const double Fa = a.f_min + (double)(a_row * 64) * a.df;
+    const double Fa = a.f_min + (double)(a_row * BW) * a.df;
 
-    floatx16 acc[2][4];  // [b half][ReX, ImX, ReZ, ImZ]
+    floatx16 acc[NB][NACC];
 #pragma unroll
-    for (int n = 0; n < 2; ++n)
+    for (int n = 0; n < NB; ++n)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[n][q] = floatx16{};
+        for (int q = 0; q < NACC; ++q) acc[n][q] = floatx16{};
 
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();  // the previous block's LDS is consumed
         if (tid < kMB) {
             const int64_t j = j0 + tid;
-            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0
+            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0 (GLS: w = 0)
             S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
             S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
+            if (GLS) S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
         }
         __syncthreads();
-        // R operands: 64 b x 4 groups of 8 samples, one task per thread and round
-        for (int task = tid; task < 64 * (kMB / 8); task += blockDim.x) {
+        // R operands: BW b x 4 groups of 8 samples
+        for (int task = tid; task < BW * (kMB / 8); task += blockDim.x) {
             const int b = task / (kMB / 8);
             const int g = task % (kMB / 8);
             const double bdf = (double)b * a.df;
@@ -127,7 +184,7 @@ __global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
         for (int ks = 0; ks < kMB / 16; ++ks) {
             const int js = 16 * ks + 8 * half;
             // this lane's L operands: a-row `row`, samples js .. js+7
-            halfx8 lrh, lrl, lih, lil, nih, nil, zrh, zrl, zih, zil, nzh, nzl;
+            COp L, L2, LW;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 double p = Fa * S.t[js + i];
@@ -136,14 +193,17 @@ __global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
                 const float c = cos_rev(ph), s = sin_rev(ph);
                 const float xv = S.x[js + i];
                 const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
-                _Float16 h, l;
-                split16(xv * c, h, l); lrh[i] = h; lrl[i] = l;
-                split16(xv * s, h, l); lih[i] = h; lil[i] = l; nih[i] = -h; nil[i] = -l;
-                split16(c2 * kTrigScale, h, l); zrh[i] = h; zrl[i] = l;
-                split16(s2 * kTrigScale, h, l); zih[i] = h; zil[i] = l; nzh[i] = -h; nzl[i] = -l;
+                L.set(i, xv * c, xv * s);
+                if (GLS) {
+                    const float wv = S.w[js + i];
+                    LW.set(i, wv * c, wv * s);
+                    L2.set(i, wv * c2, wv * s2);
+                } else {
+                    L2.set(i, c2 * kTrigScale, s2 * kTrigScale);
+                }
             }
 #pragma unroll
-            for (int n = 0; n < 2; ++n) {
+            for (int n = 0; n < NB; ++n) {
                 const int bcol = 32 * n + row;
                 const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][bcol][js]);
                 const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][bcol][js]);
@@ -153,40 +213,54 @@ __global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
                 const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][bcol][js]);
                 const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][bcol][js]);
                 const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][bcol][js]);
-                // Re = Lr Rr - Li Ri,  Im = Lr Ri + Li Rr, each in three FP16 passes;
-                // the four sums interleaved so consecutive products are independent
-                LSP_MFMA(lrh, rrh, acc[n][0]); LSP_MFMA(lrh, rih, acc[n][1]);
-                LSP_MFMA(zrh, qrh, acc[n][2]); LSP_MFMA(zrh, qih, acc[n][3]);
-                LSP_MFMA(lrh, rrl, acc[n][0]); LSP_MFMA(lrh, ril, acc[n][1]);
-                LSP_MFMA(zrh, qrl, acc[n][2]); LSP_MFMA(zrh, qil, acc[n][3]);
-                LSP_MFMA(lrl, rrh, acc[n][0]); LSP_MFMA(lrl, rih, acc[n][1]);
-                LSP_MFMA(zrl, qrh, acc[n][2]); LSP_MFMA(zrl, qih, acc[n][3]);
-                LSP_MFMA(nih, rih, acc[n][0]); LSP_MFMA(lih, rrh, acc[n][1]);
-                LSP_MFMA(nzh, qih, acc[n][2]); LSP_MFMA(zih, qrh, acc[n][3]);
-                LSP_MFMA(nih, ril, acc[n][0]); LSP_MFMA(lih, rrl, acc[n][1]);
-                LSP_MFMA(nzh, qil, acc[n][2]); LSP_MFMA(zih, qrl, acc[n][3]);
-                LSP_MFMA(nil, rih, acc[n][0]); LSP_MFMA(lil, rrh, acc[n][1]);
-                LSP_MFMA(nzl, qih, acc[n][2]); LSP_MFMA(zil, qrh, acc[n][3]);
+                if (GLS) {
+                    LSP_CMAC(LW, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
+                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][2], acc[n][3]);
+                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][4], acc[n][5]);
+                } else {
+                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
+                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][2], acc[n][3]);
+                }
             }
         }
     }
 
+    const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
+    if (GLS) {
+        const float uw = ldexpf(1.0f, ew - 28);   // 1 / (wscale 2^14)
+#pragma unroll
+        for (int n = 0; n < NB; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+                const int64_t k = ar * BW + 32 * n + row;
+                if (k < a.Nf) {
+                    float *p = a.part + (int64_t)split * 6 * a.Nf + k;
+                    p[0] = acc[n][0][r] * uw;
+                    p[a.Nf] = acc[n][1][r] * uw;
+                    p[2 * a.Nf] = acc[n][2][r] * ux;
+                    p[3 * a.Nf] = acc[n][3][r] * ux;
+                    p[4 * a.Nf] = 0.5f * acc[n][4][r] * uw;
+                    p[5 * a.Nf] = 0.5f * acc[n][5][r] * uw;
+                }
+            }
+        return;
+    }
     // FP32 chunk sums, scales removed.  The merge subtracts one per sample that
     // pads the series to whole 64-sample tiles (what the other kernels' neutral
     // samples add to CC); here the ragged end is padded to 32 samples, whose
     // pads add 1 to Re of the second product, so CC gets the difference.
-    const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
     const float uz = 1.0f / (kTrigScale * kTrigScale);
     const int64_t len = je - jb;
     const int64_t p32 = (len + kMB - 1) / kMB * kMB - len;
     const int64_t p64 = (len + kTile - 1) / kTile * kTile - len;
     const float count = (float)(len - p32 + 2 * p64);
 #pragma unroll
-    for (int n = 0; n < 2; ++n)
+    for (int n = 0; n < NB; ++n)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-            const int64_t k = ar * 64 + 32 * n + row;
+            const int64_t k = ar * BW + 32 * n + row;
             if (k < a.Nf) {
                 float *p = a.part + (int64_t)split * 4 * a.Nf + k;
                 p[0] = acc[n][0][r] * ux;
@@ -197,5 +271,57 @@ __global__ void __launch_bounds__(256) pgram_mfma_kernel(PgramArgs a)
         }
 }
 
+__global__ void __launch_bounds__(256, 2) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }
+
+__global__ void __launch_bounds__(256, 2) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
+
+// FP64 merge of the six chunk sums and the generalized power (Section 6.3):
+//   CC = sum w cos^2 - C^2, SS = sum w sin^2 - S^2, CS = sum w cos sin - C S,
+//   p = (SS YC^2 + CC YS^2 - 2 CS YC YS) / (YY (CC SS - CS^2)),
+// with sum w cos^2 = (1 + Re)/2, sum w sin^2 = 1 - that, sum w cos sin = Im/2
+// (weights normalized to 1).  The FP32 chunk sums carry absolute errors of a
+// few 1e-7, so a direction with CC or SS <= 1e-5 counts as degenerate (f near
+// 0): the fit falls back to the other direction alone, else p = 0.
+__global__ void __launch_bounds__(256) gls_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
+                                                         const CurveStats *__restrict__ st, float *__restrict__ P)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= Nf) return;
+    double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int s = 0; s < splits; ++s)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) v[q] += (double)part[((int64_t)s * 6 + q) * Nf + k];
+    const double C = v[0], Sn = v[1], YC = v[2], YS = v[3];
+    const double CCh = 0.5 + v[4], CSh = v[5];
+    const double CC = CCh - C * C, SS = (1.0 - CCh) - Sn * Sn, CS = CSh - C * Sn;
+    const double D = CC * SS - CS * CS;
+    const double YY = st->var;
+    double p = 0.0;
+    const double eps = 1e-5;
+    if (YY > 0.0) {
+        if (CC > eps && SS > eps && D > eps * eps)
+            p = (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
+        else if (CC > eps)
+            p = YC * YC / (YY * CC);
+        else if (SS > eps)
+            p = YS * YS / (YY * SS);
+    }
+    P[k] = (float)p;
+}
+
+hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int64_t per_wave = 32 * 32;
+    const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
+    const int64_t nblk = (nfb + waves - 1) / waves;
+    if (ev0) hipEventRecord(ev0, s);
+    hipLaunchKernelGGL(gls_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
+    if (ev1) hipEventRecord(ev1, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(gls_reduce_kernel, dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
+                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn);
+    return hipGetLastError();
+}
 
 }  // namespace lsp

@@ -100,6 +100,24 @@ def test_validation_happens_before_any_gpu_work():
         lsp.LSP_ERR_UNSUPPORTED
 
 
+def test_generalized_periodogram_validation_on_host():
+    L = lsp.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(16)
+    cases = [
+        (null, fake, null, 10, 0.1, 0.1, 10, fake, 0, 0),   # null t
+        (fake, null, null, 10, 0.1, 0.1, 10, fake, 0, 0),   # null y
+        (fake, fake, null, 2, 0.1, 0.1, 10, fake, 0, 0),    # Nt < 3
+        (fake, fake, null, 10, 0.1, 0.0, 10, fake, 0, 0),   # df = 0
+        (fake, fake, null, 10, 0.1, 0.1, 0, fake, 0, 0),    # Nf = 0
+        (fake, fake, null, 10, 0.1, 0.1, 10, null, 0, 0),   # null p
+        (fake, fake, null, 10, 0.1, 0.1, 10, fake, 3, 0),   # waves = 3
+        (fake, fake, null, 10, 0.1, 0.1, 10, fake, 4, -1),  # negative splits
+    ]
+    for c in cases:
+        assert L.lsp_gls(*c, null) == lsp.LSP_ERR_INVALID_ARG, c
+
+
 def test_batched_validation_on_host():
     L = lsp.lib()
     null = ctypes.c_void_p(0)
