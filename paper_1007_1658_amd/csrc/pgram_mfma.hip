@@ -48,7 +48,7 @@ struct MfmaLds {
     float x[kMB];
     float w[GLS ? kMB : 1];
     float red[2][kMaxWaves];
-    _Float16 R[R_KINDS][32 * NB][kMRow];
+    alignas(16) _Float16 R[R_KINDS][32 * NB][kMRow];  // 16-B rows: whole-row b128 reads and writes
 };
 
 __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
