@@ -21,7 +21,7 @@
 //
 // Work split: a workgroup of W waves owns a-rows [32 W blockIdx.x, +32 W) and
 // all b; wave w owns 32 a-rows (one 32 x 64 output tile per sum).  Per
-// block of 32 samples the workgroup writes the R operands once to LDS (shared
+// block of 64 samples the workgroup writes the R operands once to LDS (shared
 // by its waves); each lane builds its own L operands in registers.
 //
 // The same products give the generalized (floating-mean, weighted)
@@ -36,8 +36,8 @@ namespace lsp {
 typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-constexpr int kMB = 32;        // samples per LDS block (two K-steps of 16)
-constexpr int kMRow = kMB + 8; // halfs per LDS row: 80 B, so 16 lanes' 16-B reads hit distinct banks
+constexpr int kMB = 64;        // samples per LDS block (four K-steps of 16)
+constexpr int kMRow = kMB + 8; // halfs per LDS row: 144 B, so 16 lanes' 16-B reads hit distinct banks
 constexpr float kTrigScale = 16384.0f;  // 2^14
 
 enum { RR_H = 0, RR_L, RI_H, RI_L, R2R_H, R2R_L, R2I_H, R2I_L, R_KINDS };
@@ -248,7 +248,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
     }
     // FP32 chunk sums, scales removed.  The merge subtracts one per sample that
     // pads the series to whole 64-sample tiles (what the other kernels' neutral
-    // samples add to CC); here the ragged end is padded to 32 samples, whose
+    // samples add to CC); here the ragged end is padded to a whole block, whose
     // pads add 1 to Re of the second product, so CC gets the difference.
     const float uz = 1.0f / (kTrigScale * kTrigScale);
     const int64_t len = je - jb;
