@@ -351,7 +351,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        # matrix-core form: FP16 hi/lo products (three passes) with FP32 accumulation
+        "dtype": "f16x3/f32" if mfma else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "name": args.config, "Nt": curve.Nt, "Nf": curve.Nf,
                    "phase": "split", "tile": tile},
