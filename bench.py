@@ -166,6 +166,9 @@ def run_batched(args):
     import torch
     import paper_1007_1658_amd as lsp
     from paper_1007_1658_amd import synth
+    if args.batched_form:
+        lsp.lsp_set_batched_form(args.batched_form)
+    mfma = lsp.lsp_get_batched_form() == "mfma"
     b = synth.c3()
     t = torch.from_numpy(b.t).cuda()
     x = torch.from_numpy(b.x).cuda()
@@ -195,14 +198,18 @@ def run_batched(args):
     line = {
         "metric": METRIC + " [batched]", "value": terms / sec, "unit": "terms/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOADS["c3"], "name": "c3", "curves": b.n, "terms": terms},
+        "scaling": "weak", "vs_baseline": None, "dtype": "f16x3/f32" if mfma else "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c3"], "name": "c3", "curves": b.n, "terms": terms,
+                   "form": lsp.lsp_get_batched_form()},
         "latency_ms": {"run_p50": float(np.percentile(lat_run, 50)), "run_p99": float(np.percentile(lat_run, 99)),
                        "done_p50": float(np.percentile(lat_done, 50)), "done_p99": float(np.percentile(lat_done, 99))},
         "peak_rel_err_sampled": worst,
-        "roofline": {"bound": "alu", "achieved": FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP32_TFLOPS,
-                     "unit": "TFLOP/s", "frac": FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP32_TFLOPS,
-                     "traffic": None, "kernel": "batch_pgram_kernel (whole graph)"},
+        "roofline": ({"bound": "mfma", "achieved": MFMA_FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP16_TFLOPS,
+                      "unit": "TFLOP/s", "frac": MFMA_FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP16_TFLOPS,
+                      "traffic": None, "kernel": "batch_mfma_kernel (whole graph)"} if mfma else
+                     {"bound": "alu", "achieved": FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP32_TFLOPS,
+                      "unit": "TFLOP/s", "frac": FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP32_TFLOPS,
+                      "traffic": None, "kernel": "batch_pgram_kernel (whole graph)"}),
     }
     print(json.dumps(line), flush=True)
 
@@ -260,6 +267,8 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic launch shape")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--batched-form", default="", choices=["", "mfma", "recur"],
+                    help="c3: kernel form of the batched path (default: the library's, matrix cores)")
     ap.add_argument("--save-tune", default="", help="write the tuner cache to this JSON file")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (HBM counter calibration)")

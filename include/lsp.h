@@ -193,6 +193,17 @@ lsp_status lsp_periodogram_batched(const double *t, const float *x,
                                    int64_t *kbest, double *fbest,
                                    uint64_t *t_ns, void *stream);
 
+/* Kernel form of lsp_periodogram_batched, lsp_mc_maxpower and
+   lsp_window_features, process-wide: LSP_TRIG_MFMA (default; a persistent
+   workgroup takes (curve, 8192-frequency block) items and runs the
+   matrix-core products of LSP_TRIG_MFMA over the whole curve, FP32 sums,
+   FP64 epilogue) or LSP_TRIG_RECUR (a persistent wave takes (curve,
+   512-frequency block) items; FP32 recurrence with compensated sums).
+   LSP_ERR_INVALID_ARG for anything else.  Host-only; do not change it while
+   a call on another thread is running. */
+lsp_status lsp_set_batched_form(int32_t trig);
+int32_t lsp_get_batched_form(void);
+
 /* ---- Monte-Carlo noise periodograms (Section 6.2: simulations of the
    periodogram's statistics are the other use the paper names) ----------------
 

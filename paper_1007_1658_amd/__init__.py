@@ -99,6 +99,8 @@ SIGNATURES = {
     "lsp_tune_lookup": (_I32, [_I64, _I64, _I32, ctypes.POINTER(lsp_tile)]),
     "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
     "lsp_gls": (_I32, [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _I32, _P]),
+    "lsp_set_batched_form": (_I32, [_I32]),
+    "lsp_get_batched_form": (_I32, []),
     "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
     "lsp_tune_cache_load": (_I32, [ctypes.c_char_p]),
     "lsp_microbench": (_I32, [_I32, _I32, _I32, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -200,6 +202,16 @@ def _ptr(a):
 def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None):
     """Pn[k] = Pn(f_min + k df), k < Nf, for device t (float64) and x (float32)."""
     return lsp_periodogram_ex(t, x, f_min, df, Nf, Pn=Pn, stream=stream)
+
+
+def lsp_set_batched_form(trig):
+    """Kernel form of the batched / Monte-Carlo / window paths: "mfma" or "recur"."""
+    _check(lib().lsp_set_batched_form(TRIGS[trig] if isinstance(trig, str) else int(trig)), "lsp_set_batched_form")
+
+
+def lsp_get_batched_form() -> str:
+    v = int(lib().lsp_get_batched_form())
+    return {LSP_TRIG_RECUR: "recur", LSP_TRIG_MFMA: "mfma"}.get(v, str(v))
 
 
 def lsp_gls(t, y, f_min: float, df: float, Nf: int, w=None, p=None, waves=0, splits=0, stream=None):

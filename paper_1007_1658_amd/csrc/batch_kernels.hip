@@ -16,7 +16,7 @@
 namespace lsp {
 
 constexpr int kBatchM = 8;
-int batched_m() { return kBatchM; }
+int batched_freq_per_item(int form) { return form == LSP_TRIG_MFMA ? kBatchMfmaFreq : kWave * kBatchM; }
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds of two
@@ -247,15 +247,16 @@ __global__ void __launch_bounds__(256) batch_final_kernel(BatchArgs a, double ns
     }
 }
 
-hipError_t batched_occupancy(int waves, int *blocks_per_cu)
+hipError_t batched_occupancy(int form, int waves, int *blocks_per_cu)
 {
+    if (form == LSP_TRIG_MFMA) return batch_mfma_occupancy(blocks_per_cu);
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_pgram_kernel<kBatchM>,
                                                         kWave * waves, 0);
 }
 
-hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves, hipStream_t s)
+hipError_t launch_batched(const BatchArgs &a, int form, int persistent_blocks, int waves, hipStream_t s)
 {
-    if (m != kBatchM) return hipErrorInvalidValue;
+    if (form != LSP_TRIG_RECUR && form != LSP_TRIG_MFMA) return hipErrorInvalidValue;
     int dev = 0;
     hipGetDevice(&dev);
     int rate_khz = 0;
@@ -270,8 +271,13 @@ hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int 
         hipLaunchKernelGGL(batch_value_kernel<VAL_ONES>, dim3((unsigned)a.n_curves), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(batch_value_kernel<VAL_INPUT>, dim3((unsigned)a.n_curves), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(batch_pgram_kernel<kBatchM>, dim3((unsigned)persistent_blocks), dim3(kWave * waves), 0,
-                       s, a);
+    if (form == LSP_TRIG_MFMA) {
+        hipError_t e = launch_batch_mfma(a, persistent_blocks, s);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(batch_pgram_kernel<kBatchM>, dim3((unsigned)persistent_blocks), dim3(kWave * waves), 0,
+                           s, a);
+    }
     hipLaunchKernelGGL(batch_final_kernel, dim3(nb_c), dim3(256), 0, s, a, ns_per_tick);
     return hipGetLastError();
 }

@@ -138,10 +138,16 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 constexpr int kGlsFreqPerWave = 32 * 32;
 
 // ---- batched launchers (batch_kernels.hip) ---------------------------------------
-hipError_t launch_batched(const BatchArgs &a, int m, int persistent_blocks, int waves,
+// form: LSP_TRIG_RECUR (per-wave items of 64 kBatchM frequencies, VALU) or
+// LSP_TRIG_MFMA (per-workgroup items of kBatchMfmaFreq frequencies, matrix cores)
+hipError_t launch_batched(const BatchArgs &a, int form, int persistent_blocks, int waves,
                           hipStream_t s);
-int batched_m();
-hipError_t batched_occupancy(int waves, int *blocks_per_cu);
+int batched_freq_per_item(int form);
+hipError_t batched_occupancy(int form, int waves, int *blocks_per_cu);
+// the matrix-core persistent kernel (pgram_mfma.hip), 256 threads per workgroup
+constexpr int kBatchMfmaFreq = 4 * 32 * 64;
+hipError_t batch_mfma_occupancy(int *blocks_per_cu);
+hipError_t launch_batch_mfma(const BatchArgs &a, int persistent_blocks, hipStream_t s);
 // window-power band features of each group (curves = groups, EPI_WINDOW done)
 hipError_t launch_window_features(const BatchArgs &a, float *feat, int n_feat, hipStream_t s);
 // n standard normal deviates of counter stream `curve` (testing the generator)

@@ -380,10 +380,13 @@ struct BatchPlan {
 // Groups are given by off[] (host, CSR over t); curve c of group g uses the
 // grid of g.  reps curves per group (Monte Carlo), values laid out curve by
 // curve.  Items in longest-processing-time order.
+// kernel form of the batched, Monte-Carlo and window paths (lsp_set_batched_form)
+int g_batch_form = LSP_TRIG_MFMA;
+
 void build_plan(const int64_t *off, int32_t n_groups, const double *f_min, const double *df, const int64_t *Nf,
                 int32_t reps, BatchPlan &P)
 {
-    const int64_t per_wave = (int64_t)kWave * batched_m();
+    const int64_t per_wave = batched_freq_per_item(g_batch_form);
     P.groups.resize((size_t)n_groups);
     P.curves.resize((size_t)n_groups * (size_t)reps);
     int64_t xoff = 0, pn = 0;
@@ -424,6 +427,7 @@ void build_plan(const int64_t *off, int32_t n_groups, const double *f_min, const
 uint64_t plan_hash(const BatchPlan &P)
 {
     uint64_t h = 1469598103934665603ull;
+    h = fnv1a(h, &g_batch_form, sizeof(g_batch_form));
     h = fnv1a(h, P.groups.data(), sizeof(BatchGroup) * P.groups.size());
     h = fnv1a(h, P.curves.data(), sizeof(BatchCurve) * P.curves.size());
     return h;
@@ -508,7 +512,7 @@ lsp_status upload_plan(char *b, const BatchLayout &L, const BatchPlan &P, hipStr
 lsp_status persistent_blocks(const DeviceInfo *di, int waves, int *blocks)
 {
     int per_cu = 0;
-    hipError_t e = batched_occupancy(waves, &per_cu);
+    hipError_t e = batched_occupancy(g_batch_form, waves, &per_cu);
     if (e != hipSuccess) return hip_fail(e, "occupancy query");
     *blocks = std::max(1, per_cu) * di->cus;
     return LSP_OK;
@@ -585,7 +589,7 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
 
     hipError_t e;
     if (capturing || s == nullptr) {
-        e = launch_batched(a, batched_m(), blocks, waves, s);
+        e = launch_batched(a, g_batch_form, blocks, waves, s);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
         return LSP_OK;
     }
@@ -597,7 +601,7 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
     }
     e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-    hipError_t el = launch_batched(a, batched_m(), blocks, waves, s);
+    hipError_t el = launch_batched(a, g_batch_form, blocks, waves, s);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(s, &g);
     if (el != hipSuccess) {
@@ -651,7 +655,7 @@ static lsp_status mc_or_window(const double *t, const int64_t *off, int32_t n, c
     int blocks = 0;
     st = persistent_blocks(di, waves, &blocks);
     if (st != LSP_OK) return st;
-    hipError_t e = launch_batched(a, batched_m(), blocks, waves, s);
+    hipError_t e = launch_batched(a, g_batch_form, blocks, waves, s);
     if (e == hipSuccess && window) e = launch_window_features(a, feat, kFeatures, s);
     if (e != hipSuccess) return hip_fail(e, window ? "window features launch" : "Monte-Carlo launch");
     return LSP_OK;
@@ -846,6 +850,19 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, 
     if (e != hipSuccess) return hip_fail(e, "generalized periodogram launch");
     return LSP_OK;
 }
+
+lsp_status lsp_set_batched_form(int32_t trig)
+{
+    if (trig != LSP_TRIG_RECUR && trig != LSP_TRIG_MFMA) {
+        g_last_error = "batched form must be LSP_TRIG_RECUR or LSP_TRIG_MFMA";
+        return LSP_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    g_batch_form = trig;
+    return LSP_OK;
+}
+
+int32_t lsp_get_batched_form(void) { return g_batch_form; }
 
 lsp_status lsp_periodogram(const double *t, const float *x, int64_t Nt, double f_min, double df,
                            int64_t Nf, float *Pn, void *stream)

@@ -275,6 +275,181 @@ __global__ void __launch_bounds__(256, 2) pgram_mfma_kernel(PgramArgs a) { mfma_
 
 __global__ void __launch_bounds__(256, 2) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
 
+// ---------------------------------------------------------------------------
+// Batched form: a persistent workgroup takes (curve, block of 4 x 32 a-rows =
+// 8192 frequencies) items from the queue (longest curves first) and runs the
+// products above over the whole curve, then evaluates Eq. (5) in FP64 from the
+// FP32 sums and folds (Pn, k) into the curve's 64-bit max key.
+
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, kWave);
+        v = (w > v) ? w : v;
+    }
+    return v;
+}
+
+// Eq. (5) of the per-frequency sums, or the window power for unit values;
+// out of line so that its FP64 constants stay out of the product loop's registers
+__device__ __noinline__ float mfma_batch_epilogue(double XC, double XS, double CC, double CS, double Nt,
+                                                  double inv_var, int epi)
+{
+    if (epi == EPI_WINDOW) return (float)(XC * XC + XS * XS);
+    return pn_from_sums(XC, XS, CC, CS, Nt, inv_var);
+}
+
+__global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
+{
+    __shared__ MfmaLds<2, false> S;
+    __shared__ unsigned int s_item;
+    const int tid = threadIdx.x;
+    const int nw = blockDim.x / kWave;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int half = lane >> 5;
+    const int row = lane & 31;
+    // A workgroup never takes more than n_items items: the bound is a guaranteed
+    // exit on top of the drained-queue test, which every thread sees alike.
+    for (int guard = 0; guard <= a.n_items; ++guard) {
+        if (tid == 0) s_item = atomicAdd(a.queue, 1u);
+        __syncthreads();
+        const unsigned int it = s_item;
+        __syncthreads();  // every thread has read s_item before the next write
+        if (it >= (unsigned)a.n_items) break;
+        const BatchItem item = a.items[it];
+        const BatchCurve cv = a.curves[item.curve];
+        if (tid == 0) atomicMin(&a.tbeg[item.curve], (unsigned long long)wall_clock64());
+        const float *th = a.th + cv.toff;
+        const float *tl = a.tl + cv.toff;
+        const float *xr = a.xv + cv.xoff;
+        const int64_t Nt = cv.Nt;
+
+        float mx = 0.f;
+        for (int64_t j = tid; j < Nt; j += blockDim.x) mx = fmaxf(mx, fabsf(xr[j]));
+        mx = wave_max(mx);
+        if (lane == 0) S.red[0][wave] = mx;
+        __syncthreads();
+        mx = S.red[0][0];
+        for (int w = 1; w < nw; ++w) mx = fmaxf(mx, S.red[0][w]);
+        int ex = 0;
+        (void)frexpf(mx, &ex);
+        const float xscale = ldexpf(1.0f, 14 - ex);
+
+        const int64_t a0 = ((int64_t)item.fblock * nw + wave) * 32;
+        const double Fa = cv.f_min + (double)((a0 + row) * 64) * cv.df;
+        floatx16 acc[2][4];
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[n][q] = floatx16{};
+
+        for (int64_t j0 = 0; j0 < Nt; j0 += kMB) {
+            __syncthreads();
+            if (tid < kMB) {
+                const int64_t j = j0 + tid;
+                const bool ok = j < Nt;
+                S.t[tid] = ok ? (double)th[j] + (double)tl[j] : 0.0;
+                S.x[tid] = ok ? xr[j] * xscale : 0.0f;
+            }
+            __syncthreads();
+            for (int task = tid; task < 64 * (kMB / 8); task += blockDim.x) {
+                const int b = task / (kMB / 8);
+                const int g = task % (kMB / 8);
+                const double bdf = (double)b * cv.df;
+                halfx8 v[R_KINDS];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    double p = bdf * S.t[8 * g + i];
+                    p -= rint(p);
+                    const float ph = (float)p;
+                    const float c = cos_rev(ph), s = sin_rev(ph);
+                    const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
+                    _Float16 h, l;
+                    split16(c * kTrigScale, h, l); v[RR_H][i] = h; v[RR_L][i] = l;
+                    split16(s * kTrigScale, h, l); v[RI_H][i] = h; v[RI_L][i] = l;
+                    split16(c2 * kTrigScale, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
+                    split16(s2 * kTrigScale, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
+                }
+#pragma unroll
+                for (int q = 0; q < R_KINDS; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < kMB / 16; ++ks) {
+                const int js = 16 * ks + 8 * half;
+                COp L, L2;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    double p = Fa * S.t[js + i];
+                    p -= rint(p);
+                    const float ph = (float)p;
+                    const float c = cos_rev(ph), s = sin_rev(ph);
+                    const float xv = S.x[js + i];
+                    const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
+                    L.set(i, xv * c, xv * s);
+                    L2.set(i, c2 * kTrigScale, s2 * kTrigScale);
+                }
+#pragma unroll
+                for (int n = 0; n < 2; ++n) {
+                    const int bcol = 32 * n + row;
+                    const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][bcol][js]);
+                    const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][bcol][js]);
+                    const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[RI_H][bcol][js]);
+                    const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[RI_L][bcol][js]);
+                    const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&S.R[R2R_H][bcol][js]);
+                    const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][bcol][js]);
+                    const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][bcol][js]);
+                    const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][bcol][js]);
+                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
+                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][2], acc[n][3]);
+                }
+            }
+        }
+
+        // whole-curve sums; the ragged end was padded with samples at t' = 0,
+        // x = 0, each adding 1 to Re of the double-angle sum
+        const double ux = ldexp(1.0, ex - 28);
+        const double uz = 1.0 / ((double)kTrigScale * (double)kTrigScale);
+        const double pads = (double)((Nt + kMB - 1) / kMB * kMB - Nt);
+        const double inv_var = a.stats[item.curve].inv_var;
+        unsigned long long best = 0ull;
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t k = (a0 + 8 * (r / 4) + 4 * half + (r % 4)) * 64 + 32 * n + row;
+                if (k < cv.Nf) {
+                    const double XC = (double)acc[n][0][r] * ux, XS = (double)acc[n][1][r] * ux;
+                    const double CC = 0.5 * ((double)Nt + (double)acc[n][2][r] * uz - pads);
+                    const double CS = 0.5 * (double)acc[n][3][r] * uz;
+                    const float P = mfma_batch_epilogue(XC, XS, CC, CS, (double)Nt, inv_var, a.epi_mode);
+                    if (a.Pn) a.Pn[cv.pn_off + k] = P;
+                    const unsigned long long key = ((unsigned long long)__float_as_uint(P) << 32) |
+                                                   (unsigned long long)(0xffffffffu - (unsigned)k);
+                    best = (key > best) ? key : best;
+                }
+            }
+        best = wave_max_key(best);
+        if (lane == 0) {
+            atomicMax(&a.key[item.curve], best);
+            atomicMax(&a.tend[item.curve], (unsigned long long)wall_clock64());
+        }
+    }
+}
+
+hipError_t batch_mfma_occupancy(int *blocks_per_cu)
+{
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_mfma_kernel, 256, 0);
+}
+
+hipError_t launch_batch_mfma(const BatchArgs &a, int persistent_blocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_mfma_kernel, dim3((unsigned)persistent_blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 // FP64 merge of the six chunk sums and the generalized power (Section 6.3):
 //   CC = sum w cos^2 - C^2, SS = sum w sin^2 - S^2, CS = sum w cos sin - C S,
 //   p = (SS YC^2 + CC YS^2 - 2 CS YC YS) / (YY (CC SS - CS^2)),

@@ -146,3 +146,13 @@ def test_no_device_reported_without_gpu():
     fake = ctypes.c_void_p(16)
     st = L.lsp_periodogram(fake, fake, 10, 0.1, 0.1, 10, fake, ctypes.c_void_p(0))
     assert st == lsp.LSP_ERR_NO_DEVICE
+
+
+def test_batched_form_switch_on_host():
+    L = lsp.lib()
+    assert L.lsp_set_batched_form(7) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_set_batched_form(lsp.LSP_TRIG_DIRECT) == lsp.LSP_ERR_INVALID_ARG
+    lsp.lsp_set_batched_form("recur")
+    assert lsp.lsp_get_batched_form() == "recur"
+    lsp.lsp_set_batched_form("mfma")
+    assert lsp.lsp_get_batched_form() == "mfma"

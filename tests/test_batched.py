@@ -15,6 +15,15 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_1007_1658_amd as lsp  # noqa: E402
 
 
+@pytest.fixture(params=["mfma", "recur"], autouse=True)
+def batched_form(request):
+    """Every test here runs on both kernel forms of the batched path."""
+    print(f"batched form {request.param}", flush=True)
+    lsp.lsp_set_batched_form(request.param)
+    yield request.param
+    lsp.lsp_set_batched_form("mfma")
+
+
 def _dev(b):
     return (torch.from_numpy(b.t).cuda(), torch.from_numpy(b.x).cuda())
 
