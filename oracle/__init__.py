@@ -39,6 +39,8 @@ def _lib():
         lib.oracle_window.restype = i32
         lib.oracle_gls.argtypes = [P, P, P, i64, d, d, P, i64, P, i32]
         lib.oracle_gls.restype = i32
+        lib.oracle_mh.argtypes = [P, P, P, i64, i32, d, d, P, i64, P, i32]
+        lib.oracle_mh.restype = i32
         lib.oracle_max_threads.argtypes = []
         lib.oracle_max_threads.restype = i32
         lib.oracle_philox4x32_10.argtypes = [P, P, P]
@@ -136,6 +138,36 @@ def gls(t, y, f_min, df, Nf=None, k=None, w=None, threads=0):
         raise OracleError("zero variance")
     if rc != 0:
         raise OracleError(f"oracle_gls failed ({rc})")
+    return out
+
+
+def multiharmonic(t, y, K, f_min, df, Nf=None, k=None, w=None, threads=0):
+    """Multi-harmonic periodogram p_K(f_k) in FP64: the weighted least-squares
+    fraction of variance explained by c + sum_{h<=K} (a_h cos h wt + b_h sin h wt)."""
+    t = _f64(t)
+    y = _f64(y)
+    if t.shape != y.shape or t.ndim != 1:
+        raise OracleError("t and y must be 1-D of equal length")
+    wp = None
+    if w is not None:
+        w = _f64(w)
+        if w.shape != t.shape:
+            raise OracleError("w must match t")
+        wp = _ptr(w)
+    if k is None:
+        if Nf is None:
+            raise OracleError("give Nf or k")
+        kp, n_out = None, int(Nf)
+    else:
+        kk = np.ascontiguousarray(np.asarray(k, dtype=np.int64))
+        kp, n_out = _ptr(kk), kk.size
+    out = np.empty(n_out, dtype=np.float64)
+    rc = _lib().oracle_mh(_ptr(t), _ptr(y), wp, t.size, int(K), float(f_min), float(df), kp, n_out, _ptr(out),
+                          int(threads))
+    if rc == ZERO_VARIANCE:
+        raise OracleError("zero variance")
+    if rc != 0:
+        raise OracleError(f"oracle_mh failed ({rc})")
     return out
 
 

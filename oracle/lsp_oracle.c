@@ -416,6 +416,133 @@ int oracle_gls(const double *t, const double *y, const double *w_in, int64_t Nt,
     return ORACLE_OK;
 }
 
+/* ---- multi-harmonic periodogram ------------------------------------------
+
+   Section 6.3 also names the multi-harmonic periodogram of
+   Schwarzenberg-Czerny (1996).  Its definition is the weighted least-squares
+   fit of a constant plus K harmonics of the trial frequency,
+       y_j ~ c + sum_{h=1..K} [a_h cos(h w t_j) + b_h sin(h w t_j)],
+   and the power is the fraction of the weighted variance of y it explains,
+   p_K(w) = 1 - chi2_min / chi2_0 (K = 1 is the generalized periodogram above).
+   Here the fit is done literally: the (2K+1)-column weighted normal equations
+   are formed in FP64 (Neumaier sums) and solved by Cholesky factorization;
+   p_K = (explained sum of squares) / chi2_0 with normalized weights.  A
+   system whose Cholesky pivot falls to <= 1e-12 times its diagonal (columns
+   collinear: f = 0, or K f at a Nyquist-like frequency of the sampling) drops
+   that column, i.e. fits the remaining ones.  K in 1..4. */
+
+#define MH_MAXK 4
+#define MH_MAXC (2 * MH_MAXK + 1)
+
+static double mh_one_frequency(const double *t, const double *y, const double *w, int64_t Nt,
+                               int K, double YY, double f)
+{
+    const int n = 2 * K + 1;
+    nsum G[MH_MAXC][MH_MAXC], B[MH_MAXC];
+    for (int i = 0; i < n; ++i) {
+        B[i].s = B[i].c = 0.0;
+        for (int k = 0; k < n; ++k) G[i][k].s = G[i][k].c = 0.0;
+    }
+    double col[MH_MAXC];
+    for (int64_t j = 0; j < Nt; ++j) {
+        col[0] = 1.0;
+        for (int h = 1; h <= K; ++h) {
+            double p = (double)h * f * t[j];
+            double phi = p - nearbyint(p);
+            col[2 * h - 1] = cos(TWO_PI * phi);
+            col[2 * h] = sin(TWO_PI * phi);
+        }
+        for (int i = 0; i < n; ++i) {
+            nsum_add(&B[i], w[j] * col[i] * y[j]);
+            for (int k = 0; k <= i; ++k) nsum_add(&G[i][k], w[j] * col[i] * col[k]);
+        }
+    }
+    double A[MH_MAXC][MH_MAXC], b[MH_MAXC], L[MH_MAXC][MH_MAXC];
+    for (int i = 0; i < n; ++i) {
+        b[i] = nsum_get(&B[i]);
+        for (int k = 0; k <= i; ++k) A[i][k] = A[k][i] = nsum_get(&G[i][k]);
+    }
+    /* Cholesky with column dropping: A = L L^T over the kept columns */
+    int keep[MH_MAXC];
+    double z[MH_MAXC];
+    double explained = 0.0; /* z_0^2, the constant's share, is sum w y^2 - chi2_0 */
+    for (int i = 0; i < n; ++i) {
+        keep[i] = 0;
+        double d = A[i][i];
+        for (int k = 0; k < i; ++k)
+            if (keep[k]) d -= L[i][k] * L[i][k];
+        if (!(d > 1e-12 * A[i][i]) || !(A[i][i] > 0.0)) {
+            for (int k = 0; k <= i; ++k) L[i][k] = 0.0;
+            z[i] = 0.0;
+            continue;
+        }
+        keep[i] = 1;
+        L[i][i] = sqrt(d);
+        for (int r = i + 1; r < n; ++r) {
+            double v = A[r][i];
+            for (int k = 0; k < i; ++k)
+                if (keep[k]) v -= L[r][k] * L[i][k];
+            L[r][i] = v / L[i][i];
+        }
+        /* forward substitution L z = b: explained sum of squares = |z|^2 */
+        double v = b[i];
+        for (int k = 0; k < i; ++k)
+            if (keep[k]) v -= L[i][k] * z[k];
+        z[i] = v / L[i][i];
+        if (i > 0)
+            explained += z[i] * z[i];
+    }
+    return explained / YY;
+}
+
+int oracle_mh(const double *t, const double *y, const double *w_in, int64_t Nt, int K,
+              double f_min, double df, const int64_t *klist, int64_t n_out, double *p, int nthreads)
+{
+    if (!t || !y || !p || K < 1 || K > MH_MAXK || Nt < 2 * K + 2 || n_out < 0 || !isfinite(f_min) ||
+        !isfinite(df))
+        return ORACLE_ERR_ARG;
+    double *w = (double *)malloc((size_t)Nt * sizeof(double));
+    if (!w)
+        return ORACLE_ERR_ARG;
+    nsum W = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        w[j] = w_in ? w_in[j] : 1.0;
+        if (!(w[j] >= 0.0) || !isfinite(w[j])) {
+            free(w);
+            return ORACLE_ERR_ARG;
+        }
+        nsum_add(&W, w[j]);
+    }
+    double Wt = nsum_get(&W);
+    if (!(Wt > 0.0)) {
+        free(w);
+        return ORACLE_ERR_ARG;
+    }
+    nsum Ys = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j) {
+        w[j] /= Wt;
+        nsum_add(&Ys, w[j] * y[j]);
+    }
+    double Y = nsum_get(&Ys);
+    nsum V = {0, 0};
+    for (int64_t j = 0; j < Nt; ++j)
+        nsum_add(&V, w[j] * (y[j] - Y) * (y[j] - Y));
+    double YY = nsum_get(&V);
+    if (!(YY > 0.0)) {
+        free(w);
+        return ORACLE_ERR_ZERO_VARIANCE;
+    }
+    if (nthreads <= 0)
+        nthreads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 8) num_threads(nthreads)
+    for (int64_t i = 0; i < n_out; ++i) {
+        int64_t k = klist ? klist[i] : i;
+        p[i] = mh_one_frequency(t, y, w, Nt, K, YY, f_min + (double)k * df);
+    }
+    free(w);
+    return ORACLE_OK;
+}
+
 int oracle_max_threads(void) { return omp_get_max_threads(); }
 
 /* ---- counter-based normal deviates (white-noise Monte Carlo) -------------
