@@ -163,6 +163,20 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
                    double f_min, double df, int64_t Nf, float *p, int32_t waves,
                    int32_t splits, void *stream);
 
+/* Multi-harmonic periodogram (Schwarzenberg-Czerny 1996, also named in
+   Section 6.3): the weighted least-squares fit of
+     y ~ c + sum_{h=1..K} (a_h cos h wt + b_h sin h wt)
+   and p_K = fraction of the weighted variance of y it explains (K = 1 is
+   lsp_gls).  Its normal equations need sum w e^{i m wt} for m = 1..2K and
+   sum w (y - Y) e^{i h wt} for h = 1..K: 3K complex matrix-core products;
+   the (2K x 2K) centred system is solved per frequency in FP64 by Cholesky,
+   a column whose pivot falls to <= 1e-5 of its diagonal (or whose diagonal is
+   <= 1e-5) being dropped.  K in {1, 2} (LSP_ERR_UNSUPPORTED above);
+   Nt >= 2K + 1; other arguments as lsp_gls. */
+lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, int64_t Nt,
+                             int32_t K, double f_min, double df, int64_t Nf, float *p,
+                             int32_t waves, int32_t splits, void *stream);
+
 /* ---- many light curves in one persistent launch ------------------------------
 
    Curve c owns samples [off[c], off[c+1]) of t and x and its own grid

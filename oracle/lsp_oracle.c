@@ -498,7 +498,7 @@ static double mh_one_frequency(const double *t, const double *y, const double *w
 int oracle_mh(const double *t, const double *y, const double *w_in, int64_t Nt, int K,
               double f_min, double df, const int64_t *klist, int64_t n_out, double *p, int nthreads)
 {
-    if (!t || !y || !p || K < 1 || K > MH_MAXK || Nt < 2 * K + 2 || n_out < 0 || !isfinite(f_min) ||
+    if (!t || !y || !p || K < 1 || K > MH_MAXK || Nt < 2 * K + 1 || n_out < 0 || !isfinite(f_min) ||
         !isfinite(df))
         return ORACLE_ERR_ARG;
     double *w = (double *)malloc((size_t)Nt * sizeof(double));

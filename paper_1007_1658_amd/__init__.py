@@ -100,6 +100,7 @@ SIGNATURES = {
     "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
     "lsp_gls": (_I32, [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _I32, _P]),
     "lsp_set_batched_form": (_I32, [_I32]),
+    "lsp_multiharmonic": (_I32, [_P, _P, _P, _I64, _I32, _D, _D, _I64, _P, _I32, _I32, _P]),
     "lsp_get_batched_form": (_I32, []),
     "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
     "lsp_tune_cache_load": (_I32, [ctypes.c_char_p]),
@@ -202,6 +203,28 @@ def _ptr(a):
 def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None):
     """Pn[k] = Pn(f_min + k df), k < Nf, for device t (float64) and x (float32)."""
     return lsp_periodogram_ex(t, x, f_min, df, Nf, Pn=Pn, stream=stream)
+
+
+def lsp_multiharmonic(t, y, K: int, f_min: float, df: float, Nf: int, w=None, p=None, waves=0, splits=0,
+                      stream=None):
+    """Multi-harmonic periodogram p_K[Nf] (device float32), K in {1, 2}."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(y, torch.float32, "y")
+    if t.ndim != 1 or y.shape != t.shape:
+        raise ValueError("t and y must be 1-D and of equal length")
+    if w is not None:
+        _dev_tensor(w, torch.float32, "w")
+        if w.shape != t.shape:
+            raise ValueError("w must match t")
+    if p is None:
+        p = torch.empty(int(Nf), dtype=torch.float32, device=t.device)
+    _dev_tensor(p, torch.float32, "p")
+    if p.numel() < int(Nf):
+        raise ValueError("p is shorter than Nf")
+    _check(lib().lsp_multiharmonic(_ptr(t), _ptr(y), _ptr(w), t.numel(), int(K), float(f_min), float(df), int(Nf),
+                                   _ptr(p), int(waves), int(splits), _stream_ptr(stream)), "lsp_multiharmonic")
+    return p
 
 
 def lsp_set_batched_form(trig):

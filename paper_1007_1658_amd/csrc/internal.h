@@ -135,6 +135,8 @@ __global__ void pgram_mfma_kernel(PgramArgs a);
 hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
                                 int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s);
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+// the multi-harmonic periodogram with K = 2 (pgram_mfma.hip): part[splits][12][Nf]
+hipError_t launch_mh(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;
 
 // ---- batched launchers (batch_kernels.hip) ---------------------------------------

@@ -774,10 +774,30 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, doubl
     return h.zero_var ? LSP_ERR_ZERO_VARIANCE : LSP_OK;
 }
 
+// the generalized (K = 1) and multi-harmonic (K = 2) periodograms
+static lsp_status run_weighted(const double *t, const float *y, const float *w, int64_t Nt, int K, double f_min,
+                               double df, int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream);
+
 lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, double f_min, double df,
                    int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream)
 {
-    if (!t || !y || !p || Nt < 3 || Nt > kMaxNt || Nf < 1 || Nf > kMaxNf || !finite_nonneg(f_min) ||
+    return run_weighted(t, y, w, Nt, 1, f_min, df, Nf, p, waves, splits, stream);
+}
+
+lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, int64_t Nt, int32_t K, double f_min,
+                             double df, int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream)
+{
+    if (K != 1 && K != 2) {
+        g_last_error = "harmonic count K must be 1 or 2";
+        return K < 1 ? LSP_ERR_INVALID_ARG : LSP_ERR_UNSUPPORTED;
+    }
+    return run_weighted(t, y, w, Nt, K, f_min, df, Nf, p, waves, splits, stream);
+}
+
+static lsp_status run_weighted(const double *t, const float *y, const float *w, int64_t Nt, int K, double f_min,
+                               double df, int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream)
+{
+    if (!t || !y || !p || Nt < 2 * K + 1 || Nt > kMaxNt || Nf < 1 || Nf > kMaxNf || !finite_nonneg(f_min) ||
         !finite_pos(df) || !std::isfinite(f_min + (double)(Nf - 1) * df)) {
         g_last_error = "invalid argument";
         return LSP_ERR_INVALID_ARG;
@@ -813,7 +833,8 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, 
     const size_t o_th = o, o_tl = o + fb, o_xv = o + 2 * fb, o_wv = o + 3 * fb;
     o += 4 * fb;
     const size_t o_part = o;
-    o = align_up(o + sizeof(float) * 6 * (size_t)Nf * (size_t)eff);
+    const int slots = (K == 1) ? 6 : 6 * K;  // partial sums per frequency and chunk
+    o = align_up(o + sizeof(float) * (size_t)slots * (size_t)Nf * (size_t)eff);
     StreamCtx &sc = stream_ctx(dev, s);
     st = ensure(sc.ws, o, s);
     if (st != LSP_OK) return st;
@@ -844,9 +865,9 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, 
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return hip_fail(hipGetLastError(), "hipEventCreate");
         ctx().prof_events.emplace_back(ev0, ev1);
-        ctx().prof_name = "gls_mfma_kernel";
+        ctx().prof_name = (K == 1) ? "gls_mfma_kernel" : "mh_mfma_kernel";
     }
-    e = launch_gls(a, waves, s, ev0, ev1);
+    e = (K == 1) ? launch_gls(a, waves, s, ev0, ev1) : launch_mh(a, waves, s, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "generalized periodogram launch");
     return LSP_OK;
 }

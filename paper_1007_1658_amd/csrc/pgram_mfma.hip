@@ -499,4 +499,279 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Multi-harmonic periodogram (Section 6.3's pointer to Schwarzenberg-Czerny
+// 1996): the weighted least-squares fit of c + sum_{h<=K} (a_h cos h wt +
+// b_h sin h wt).  Its normal equations need, per frequency,
+//   C_m + i S_m = sum_j w_j e^{i m w t'_j}, m = 1..2K  (Gram entries through
+//   cos A cos B = (cos(A-B) + cos(A+B))/2 and the like), and
+//   YC_h + i YS_h = sum_j w_j (y_j - Y) e^{i h w t'_j}, h = 1..K,
+// i.e. 3K complex products of the same kind, with the R operands of
+// harmonics 1..2K.  K = 2 here: b range 32 (k = 32a + b), twelve 32x32 sums
+// per wave (one wave per SIMD), 16 operand kinds in LDS.
+
+constexpr int kMhK = 2;
+
+struct MhLds {
+    double t[kMB];
+    float x[kMB];
+    float w[kMB];
+    float red[2][kMaxWaves];
+    alignas(16) _Float16 R[4 * 2 * kMhK][32][kMRow];  // harmonic m = 1..2K: (re hi, re lo, im hi, im lo)
+};
+
+// z = u v for complex u, v
+__device__ __forceinline__ void cmul(float ur, float ui, float vr, float vi, float &zr, float &zi)
+{
+    zr = ur * vr - ui * vi;
+    zi = ur * vi + ui * vr;
+}
+
+__global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
+{
+    constexpr int M2 = 2 * kMhK;       // harmonics of the C, S sums
+    constexpr int NS = 3 * kMhK;       // complex sums: M2 of weights, kMhK of values
+    __shared__ MhLds S;
+    const int tid = threadIdx.x;
+    const int nw = blockDim.x / kWave;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int half = lane >> 5;
+    const int row = lane & 31;
+    const int split = blockIdx.y;
+    const int64_t jb = (int64_t)split * a.chunk;
+    const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
+
+    float mx = 0.f, mw = 0.f;
+    for (int64_t j = jb + tid; j < je; j += blockDim.x) {
+        mx = fmaxf(mx, fabsf(a.rec.xv[j]));
+        mw = fmaxf(mw, a.rec.wv[j]);
+    }
+    mx = wave_max(mx);
+    mw = wave_max(mw);
+    if (lane == 0) {
+        S.red[0][wave] = mx;
+        S.red[1][wave] = mw;
+    }
+    __syncthreads();
+    mx = S.red[0][0];
+    mw = S.red[1][0];
+    for (int w = 1; w < nw; ++w) {
+        mx = fmaxf(mx, S.red[0][w]);
+        mw = fmaxf(mw, S.red[1][w]);
+    }
+    int ex = 0, ew = 0;
+    (void)frexpf(mx, &ex);
+    (void)frexpf(mw, &ew);
+    const float xscale = ldexpf(1.0f, 14 - ex);
+    const float wscale = ldexpf(1.0f, 14 - ew);
+
+    const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
+    const double Fa = a.f_min + (double)(a_row * 32) * a.df;
+
+    floatx16 acc[NS][2];  // [sum][re, im]: sums 0..M2-1 weights (m = 1..2K), M2.. values (h = 1..K)
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        acc[q][0] = floatx16{};
+        acc[q][1] = floatx16{};
+    }
+
+    for (int64_t j0 = jb; j0 < je; j0 += kMB) {
+        __syncthreads();
+        if (tid < kMB) {
+            const int64_t j = j0 + tid;
+            const bool ok = j < je;  // ragged end: t' = 0, x = 0, w = 0 (adds nothing)
+            S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
+            S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
+            S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
+        }
+        __syncthreads();
+        // R operands of harmonics 1..2K: 32 b x 8 groups of 8 samples
+        for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
+            const int b = task / (kMB / 8);
+            const int g = task % (kMB / 8);
+            const double bdf = (double)b * a.df;
+            halfx8 v[4 * M2];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                double p = bdf * S.t[8 * g + i];
+                p -= rint(p);
+                const float ph = (float)p;
+                const float c1 = cos_rev(ph), s1 = sin_rev(ph);
+                float cr = c1, ci = s1;
+#pragma unroll
+                for (int m = 0; m < M2; ++m) {
+                    if (m > 0) cmul(cr, ci, c1, s1, cr, ci);
+                    _Float16 h, l;
+                    split16(cr * kTrigScale, h, l);
+                    v[4 * m][i] = h;
+                    v[4 * m + 1][i] = l;
+                    split16(ci * kTrigScale, h, l);
+                    v[4 * m + 2][i] = h;
+                    v[4 * m + 3][i] = l;
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 4 * M2; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kMB / 16; ++ks) {
+            const int js = 16 * ks + 8 * half;
+            float e1r[8], e1i[8], er[8], ei[8], xv[8], wv[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                double p = Fa * S.t[js + i];
+                p -= rint(p);
+                const float ph = (float)p;
+                e1r[i] = cos_rev(ph);
+                e1i[i] = sin_rev(ph);
+                er[i] = e1r[i];
+                ei[i] = e1i[i];
+                xv[i] = S.x[js + i];
+                wv[i] = S.w[js + i];
+            }
+#pragma unroll
+            for (int m = 0; m < M2; ++m) {
+                if (m > 0) {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) cmul(er[i], ei[i], e1r[i], e1i[i], er[i], ei[i]);
+                }
+                const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[4 * m][row][js]);
+                const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 1][row][js]);
+                const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 2][row][js]);
+                const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 3][row][js]);
+                COp LW;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) LW.set(i, wv[i] * er[i], wv[i] * ei[i]);
+                LSP_CMAC(LW, rrh, rrl, rih, ril, acc[m][0], acc[m][1]);
+                if (m < kMhK) {
+                    COp LX;
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) LX.set(i, xv[i] * er[i], xv[i] * ei[i]);
+                    LSP_CMAC(LX, rrh, rrl, rih, ril, acc[M2 + m][0], acc[M2 + m][1]);
+                }
+            }
+        }
+    }
+
+    const float ux = ldexpf(1.0f, ex - 28);
+    const float uw = ldexpf(1.0f, ew - 28);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        const int64_t k = ar * 32 + row;
+        if (k < a.Nf) {
+            float *p = a.part + (int64_t)split * 2 * NS * a.Nf + k;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const float u = (q < M2) ? uw : ux;
+                p[(2 * q) * a.Nf] = acc[q][0][r] * u;
+                p[(2 * q + 1) * a.Nf] = acc[q][1][r] * u;
+            }
+        }
+    }
+}
+
+// FP64 merge and the least-squares solve.  Columns u = (cos hwt, sin hwt),
+// h = 1..K, centred by their weighted means (the constant is fitted):
+//   G_ik = sum w u_i u_k - mean_i mean_k,  b_i = sum w (y - Y) u_i,
+// with sum w cos(Aw t) cos(Bw t) = (C_{A-B} + C_{A+B})/2 and the like
+// (C_0 = 1, S_0 = 0, C_{-m} = C_m, S_{-m} = -S_m).  Cholesky with column
+// dropping (a pivot <= 1e-5 of its diagonal, or a diagonal <= 1e-5: columns
+// the FP32 sums cannot separate); p = |L^{-1} b|^2 / YY.
+__global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
+                                                        const CurveStats *__restrict__ st, float *__restrict__ P)
+{
+    constexpr int K = kMhK, M2 = 2 * kMhK, NS = 3 * kMhK, n = 2 * kMhK;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= Nf) return;
+    double v[2 * NS];
+#pragma unroll
+    for (int q = 0; q < 2 * NS; ++q) v[q] = 0.0;
+    for (int s = 0; s < splits; ++s)
+#pragma unroll
+        for (int q = 0; q < 2 * NS; ++q) v[q] += (double)part[((int64_t)s * 2 * NS + q) * Nf + k];
+    double C[M2 + 1], Sn[M2 + 1];
+    C[0] = 1.0;
+    Sn[0] = 0.0;
+#pragma unroll
+    for (int m = 1; m <= M2; ++m) {
+        C[m] = v[2 * (m - 1)];
+        Sn[m] = v[2 * (m - 1) + 1];
+    }
+    auto Cm = [&](int m) { return C[m < 0 ? -m : m]; };
+    auto Sm = [&](int m) { return m < 0 ? -Sn[-m] : Sn[m]; };
+    // column i: harmonic 1 + i/2, cos for even i, sin for odd i
+    double G[n][n], b[n], mean[n];
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        const int h = 1 + i / 2;
+        mean[i] = (i % 2 == 0) ? C[h] : Sn[h];
+        b[i] = v[2 * M2 + 2 * (h - 1) + (i % 2)];
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i)
+#pragma unroll
+        for (int j = 0; j < n; ++j) {
+            const int A = 1 + i / 2, B = 1 + j / 2;
+            double raw;
+            if (i % 2 == 0 && j % 2 == 0) raw = 0.5 * (Cm(A - B) + Cm(A + B));
+            else if (i % 2 == 1 && j % 2 == 1) raw = 0.5 * (Cm(A - B) - Cm(A + B));
+            else if (i % 2 == 0) raw = 0.5 * (Sm(A + B) - Sm(A - B));  // cos(A) sin(B)
+            else raw = 0.5 * (Sm(A + B) + Sm(A - B));                   // sin(A) cos(B)
+            G[i][j] = raw - mean[i] * mean[j];
+        }
+    const double eps = 1e-5;
+    double L[n][n], z[n];
+    bool keep[n];
+    double explained = 0.0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        keep[i] = false;
+        z[i] = 0.0;
+#pragma unroll
+        for (int c = 0; c < n; ++c) L[i][c] = 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < n; ++i) {
+        double d = G[i][i];
+#pragma unroll
+        for (int c = 0; c < i; ++c) d -= L[i][c] * L[i][c];
+        if (!(G[i][i] > eps) || !(d > eps * G[i][i])) continue;
+        keep[i] = true;
+        L[i][i] = sqrt(d);
+#pragma unroll
+        for (int r = i + 1; r < n; ++r) {
+            double t = G[r][i];
+#pragma unroll
+            for (int c = 0; c < i; ++c) t -= L[r][c] * L[i][c];
+            L[r][i] = t / L[i][i];
+        }
+        double t = b[i];
+#pragma unroll
+        for (int c = 0; c < i; ++c) t -= L[i][c] * z[c];
+        z[i] = t / L[i][i];
+        explained += z[i] * z[i];
+    }
+    (void)K;
+    const double YY = st->var;
+    P[k] = (YY > 0.0) ? (float)(explained / YY) : 0.0f;
+}
+
+hipError_t launch_mh(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    const int64_t per_wave = 32 * 32;
+    const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
+    const int64_t nblk = (nfb + waves - 1) / waves;
+    if (ev0) hipEventRecord(ev0, s);
+    hipLaunchKernelGGL(mh_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
+    if (ev1) hipEventRecord(ev1, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
+                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn);
+    return hipGetLastError();
+}
+
 }  // namespace lsp
