@@ -43,6 +43,8 @@ WORKLOADS = {
     "gls": ("generalized (floating-mean, weighted) periodogram on c1's sampling: Nt=65536, Nf=131072, "
             "weights U[0.5, 2]"),
     "mh": ("multi-harmonic periodogram, K = 2, on c1's sampling: Nt=65536, Nf=131072, weights U[0.5, 2]"),
+    "fast": ("extirpolation + FFT approximation (Press & Rybicki), macc 4, on c1: Nt=65536, Nf=131072; "
+             "Nt*Nf terms/s of the direct sums it replaces"),
 }
 GLS_FLOP_PER_TERM = 72      # three complex products in three FP16 passes: 36 multiply-adds
 MH_FLOP_PER_TERM = 144      # K = 2: six complex products in three FP16 passes: 72 multiply-adds
@@ -271,6 +273,35 @@ def run_gls(args):
     print(json.dumps(line), flush=True)
 
 
+def run_fast(args):
+    """The extirpolation + FFT approximation on c1 (not the headline): time per
+    call, its error against the direct GPU path and against the FP64 oracle."""
+    import torch
+    import paper_1007_1658_amd as lsp
+    from paper_1007_1658_amd import synth
+    c = synth.c1()
+    t = torch.from_numpy(c.t).cuda()
+    x = torch.from_numpy(c.x).cuda()
+    p = torch.empty(c.Nf, dtype=torch.float32, device="cuda")
+
+    def step():
+        lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=4, Pn=p)
+
+    step()
+    torch.cuda.synchronize()
+    err = sampled_error(c, p.cpu().numpy())
+    sec = time_steps(step, args.steps, args.warmup)
+    line = {
+        "metric": "Nt·Nf terms/s (equivalent) of the extirpolation+FFT approximation, macc 4",
+        "value": c.Nt * c.Nf / sec, "unit": "terms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": sec * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": WORKLOADS["fast"], "name": "fast", "Nt": c.Nt, "Nf": c.Nf},
+        "max_rel_err_vs_direct_oracle": err, "meets_1e-4": bool(err <= REL_TOL),
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +341,9 @@ def main():
         return
     if args.config in ("gls", "mh"):
         run_gls(args)
+        return
+    if args.config == "fast":
+        run_fast(args)
         return
     curve = make_curve(args.config)
     t = torch.from_numpy(curve.t).cuda()

@@ -138,6 +138,22 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt,
                               double f_min, double df, int64_t Nf, float *Pn,
                               void *stream, const lsp_options *opt);
 
+/* Approximate periodogram by extirpolation and FFT (Press & Rybicki 1989,
+   the approach Section 1 cites beside the direct sums), for comparison with
+   the direct path: x - mean is spread onto a periodic grid of N points
+   (period 1/df, N = smallest power of two >= 4 macc (f_max/df + 1)) with
+   the Lagrange weights of the macc nearest points, ones likewise at twice
+   the positions; both grids are Fourier transformed (hipFFT, FP64) and
+   Eq. (5) is evaluated on bins f_min/df .. f_min/df + Nf - 1.  Everything is
+   FP64; the error against the direct sums comes from the spreading only and
+   falls with macc (4, 6 or 8).  f_min must be a whole multiple of df.
+   Arguments as lsp_periodogram; the grid may need up to 2^28 points
+   (LSP_ERR_INVALID_ARG beyond).  The first call for a grid size creates an
+   FFT plan (cached per device, stream and size until the process ends).
+   Asynchronous on stream otherwise. */
+lsp_status lsp_periodogram_fast(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                                int64_t Nf, int32_t macc, float *Pn, void *stream);
+
 /* ---- generalized (floating-mean, weighted) periodogram -------------------------
 
    Section 6.3 points to the generalization of Zechmeister & Kuerster (2009):

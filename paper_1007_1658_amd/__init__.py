@@ -100,6 +100,7 @@ SIGNATURES = {
     "lsp_list_tiles": (_I32, [_I32, ctypes.POINTER(lsp_tile), _I32]),
     "lsp_gls": (_I32, [_P, _P, _P, _I64, _D, _D, _I64, _P, _I32, _I32, _P]),
     "lsp_set_batched_form": (_I32, [_I32]),
+    "lsp_periodogram_fast": (_I32, [_P, _P, _I64, _D, _D, _I64, _I32, _P, _P]),
     "lsp_multiharmonic": (_I32, [_P, _P, _P, _I64, _I32, _D, _D, _I64, _P, _I32, _I32, _P]),
     "lsp_get_batched_form": (_I32, []),
     "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
@@ -235,6 +236,23 @@ def lsp_set_batched_form(trig):
 def lsp_get_batched_form() -> str:
     v = int(lib().lsp_get_batched_form())
     return {LSP_TRIG_RECUR: "recur", LSP_TRIG_MFMA: "mfma"}.get(v, str(v))
+
+
+def lsp_periodogram_fast(t, x, f_min: float, df: float, Nf: int, macc: int = 4, Pn=None, stream=None):
+    """Approximate Pn[Nf] by extirpolation + FFT (f_min a whole multiple of df)."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(x, torch.float32, "x")
+    if t.ndim != 1 or x.shape != t.shape:
+        raise ValueError("t and x must be 1-D and of equal length")
+    if Pn is None:
+        Pn = torch.empty(int(Nf), dtype=torch.float32, device=t.device)
+    _dev_tensor(Pn, torch.float32, "Pn")
+    if Pn.numel() < int(Nf):
+        raise ValueError("Pn is shorter than Nf")
+    _check(lib().lsp_periodogram_fast(_ptr(t), _ptr(x), t.numel(), float(f_min), float(df), int(Nf), int(macc),
+                                      _ptr(Pn), _stream_ptr(stream)), "lsp_periodogram_fast")
+    return Pn
 
 
 def lsp_gls(t, y, f_min: float, df: float, Nf: int, w=None, p=None, waves=0, splits=0, stream=None):

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmi355lsp.so")
-SOURCES = ["pgram_kernels.hip", "pgram_mfma.hip", "batch_kernels.hip", "mlp_kernels.hip", "microbench.hip", "lsp_host.cpp",
+SOURCES = ["pgram_kernels.hip", "pgram_mfma.hip", "batch_kernels.hip", "mlp_kernels.hip", "microbench.hip", "fast_kernels.hip", "fast_host.cpp", "lsp_host.cpp",
            "tuner.cpp", "surrogate.cpp"]
 ARCH = os.environ.get("LSP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -47,7 +47,7 @@ def _compile(src: str, verbose: bool) -> str:
 def build(verbose: bool = False) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs + ["-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -139,6 +139,16 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 hipError_t launch_mh(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;
 
+// moments and CurveStats only (no records)
+hipError_t launch_moments(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
+                          CurveStats *stats, hipStream_t s);
+// extirpolation + FFT periodogram (fast_kernels.hip): grids = 2 N doubles (values, ones at 2u);
+// spectra = 2 (N/2 + 1) complex doubles, the two real-to-complex transforms back to back
+hipError_t launch_fast_extirp(const double *t, const float *x, int64_t Nt, const CurveStats *stats, double df,
+                              int64_t N, int macc, double *grids, hipStream_t s);
+hipError_t launch_fast_epilogue(const void *spectra, int64_t N, int64_t m0, int64_t Nf, int64_t Nt,
+                                const CurveStats *stats, float *Pn, hipStream_t s);
+
 // ---- batched launchers (batch_kernels.hip) ---------------------------------------
 // form: LSP_TRIG_RECUR (per-wave items of 64 kBatchM frequencies, VALU) or
 // LSP_TRIG_MFMA (per-workgroup items of kBatchMfmaFreq frequencies, matrix cores)

@@ -83,6 +83,15 @@ hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_
     return hipGetLastError();
 }
 
+hipError_t launch_moments(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
+                          CurveStats *stats, hipStream_t s)
+{
+    hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
+    hipLaunchKernelGGL(prep_finalize_kernel, dim3(1), dim3(256), 0, s, (const Moments *)moments,
+                       n_moment_blocks, (int)PH_NAIVE, stats);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Prep of the generalized periodogram: weighted moments (weights w_j >= 0,
 // NULL = all 1), then records t' (split), w_j (y_j - Y) / W and w_j / W.

@@ -156,3 +156,19 @@ def test_batched_form_switch_on_host():
     assert lsp.lsp_get_batched_form() == "recur"
     lsp.lsp_set_batched_form("mfma")
     assert lsp.lsp_get_batched_form() == "mfma"
+
+
+def test_fast_periodogram_validation_on_host():
+    L = lsp.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(16)
+    cases = [
+        (null, fake, 10, 0.1, 0.1, 10, 4, fake),     # null t
+        (fake, fake, 1, 0.1, 0.1, 10, 4, fake),      # Nt < 2
+        (fake, fake, 10, 0.1, 0.1, 10, 5, fake),     # macc not 4, 6, 8
+        (fake, fake, 10, 0.15, 0.1, 10, 4, fake),    # f_min not a multiple of df
+        (fake, fake, 10, 0.1, 0.0, 10, 4, fake),     # df = 0
+        (fake, fake, 10, 0.0, 1e-9, 1 << 26, 8, fake),  # grid beyond 2^28
+    ]
+    for c in cases:
+        assert L.lsp_periodogram_fast(*c, null) == lsp.LSP_ERR_INVALID_ARG, c

@@ -1,0 +1,69 @@
+"""GPU parity of the extirpolation + FFT periodogram (Press & Rybicki 1989,
+cited in Section 1) against its FP64 numpy oracle, and its approximation
+error against the direct sums."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import extirp as E
+from paper_1007_1658_amd import synth
+from util import REL_TOL
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1007_1658_amd as lsp  # noqa: E402
+
+
+def _dev(c):
+    return torch.from_numpy(c.t).cuda(), torch.from_numpy(c.x).cuda()
+
+
+@pytest.mark.parametrize("macc", [4, 6, 8])
+def test_fast_matches_its_oracle_at_full_c1_size(macc):
+    c = synth.c1()
+    t, x = _dev(c)
+    P = lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=macc).cpu().numpy().astype(np.float64)
+    ref = E.periodogram_fast(c.t, c.x, c.f_min, c.df, c.Nf, macc=macc)
+    err = np.max(np.abs(P - ref)) / ref.max()
+    print(f"fast macc={macc} vs its oracle: {err:.2e}", flush=True)
+    assert err <= 1e-6   # both FP64 up to the FP32 output
+    assert np.argmax(P) == np.argmax(ref)
+
+
+@pytest.mark.parametrize("Nt,Nf,m0", [(2, 5, 1), (3, 17, 0), (100, 1000, 1), (1000, 2000, 3), (5000, 7, 40)])
+def test_fast_small_and_offset_grids(Nt, Nf, m0):
+    g = np.random.default_rng([31, Nt, Nf])
+    tt = np.sort(g.uniform(0, 40, Nt))
+    xx = (np.sin(2 * np.pi * 0.8 * tt) + g.normal(0, 1, Nt)).astype(np.float32)
+    df = 1.0 / (4 * (tt[-1] - tt[0]))
+    c = synth.Curve(tt, xx, m0 * df, df, Nf)
+    t, x = _dev(c)
+    P = lsp.lsp_periodogram_fast(t, x, c.f_min, df, Nf, macc=6).cpu().numpy().astype(np.float64)
+    ref = E.periodogram_fast(tt, xx, c.f_min, df, Nf, macc=6)
+    assert np.max(np.abs(P - ref)) <= 1e-6 * max(ref.max(), 1e-30) + 1e-30
+
+
+def test_fast_approximation_error_against_direct_sums():
+    """The speed/accuracy trade-off: macc 4 already meets the 1e-4 bar on c0."""
+    c = synth.c0()
+    t, x = _dev(c)
+    ref = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=c.Nf)
+    errs = {}
+    for macc in (4, 6, 8):
+        P = lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=macc).cpu().numpy()
+        errs[macc] = float(np.max(np.abs(P - ref)) / ref.max())
+        assert np.argmax(P) == np.argmax(ref)
+    print("fast vs direct:", errs, flush=True)
+    assert errs[4] <= REL_TOL and errs[8] <= errs[4]
+
+
+def test_fast_rejects_offgrid_fmin():
+    c = synth.c0()
+    t, x = _dev(c)
+    with pytest.raises(lsp.LspError) as ei:
+        lsp.lsp_periodogram_fast(t, x, 0.5 * c.df, c.df, 10)
+    assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
