@@ -82,3 +82,19 @@ def test_gls_floating_mean_zero_frequency_and_degenerate_inputs():
     assert np.all(lsp.lsp_gls(td, yc, 0.0, df, Nf, w=wd).cpu().numpy() == 0.0)
     (wz,) = _dev(np.zeros(700, np.float32))
     assert np.all(lsp.lsp_gls(td, yd, 0.0, df, Nf, w=wz).cpu().numpy() == 0.0)
+
+
+def test_gls_epoch_offset_times_sampled():
+    """c2's epoch-offset times (2455000 d + 3650 d): the split FP64 phases keep
+    the generalized periodogram on the bar; oracle on sampled bins."""
+    c = synth.c2()
+    td, yd, _ = _dev(c.t, c.x, None)
+    Pg = lsp.lsp_gls(td, yd, c.f_min, c.df, c.Nf).cpu().numpy()
+    k0 = int(round((13.7 - c.f_min) / c.df))
+    g = np.random.default_rng(6)
+    k = np.unique(np.concatenate([g.integers(0, c.Nf, 200), np.arange(k0 - 5, k0 + 6)]))
+    P = oracle.gls(c.t, c.x.astype(np.float64), c.f_min, c.df, k=k)
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
+    print(f"gls c2 sampled rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert abs(int(np.argmax(Pg)) - k0) <= 1
