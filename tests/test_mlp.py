@@ -198,3 +198,33 @@ def test_short_training_reduces_loss():
     assert losses[-1] >= floor - 1e-4
     assert losses[-1] - floor < 0.5 * (losses[0] - floor)
     m.close()
+
+
+def test_truncated_or_foreign_model_file_is_rejected(tmp_path):
+    m, params, feat, y, mean, std = _model_and_data()
+    f = tmp_path / "m.bin"
+    m.save(str(f))
+    data = f.read_bytes()
+    (tmp_path / "short.bin").write_bytes(data[: len(data) // 2])
+    (tmp_path / "foreign.bin").write_bytes(b"NOT-A-MODEL-FILE" + data[16:])
+    for name in ("short.bin", "foreign.bin"):
+        with pytest.raises(lsp.LspError) as ei:
+            lsp.Model(path=str(tmp_path / name))
+        assert ei.value.status == lsp.LSP_ERR_MODEL, name
+    m.close()
+
+
+def test_out_of_range_features_route_to_monte_carlo():
+    t, off, fm, df, nf = _patterns(6, 8)
+    td = torch.from_numpy(t).cuda()
+    feat = lsp.lsp_window_features(td, off, fm, df, nf)
+    F = feat.cpu().numpy()
+    m = lsp.Model(members=2, seed=4)
+    # a feature range narrower than the patterns' own spread: every pattern is out of range
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e-3, -0.4, 0.5)
+    p_obs = torch.full((6,), 8.0, device="cuda")
+    fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=10.0, mc_realizations=64, seed=5)
+    assert used.sum().item() == 6
+    pm = lsp.lsp_mc_maxpower(td, off, fm, df, nf, 64, seed=5).cpu().numpy()
+    assert np.allclose(fap.cpu().numpy(), (pm >= 8.0).mean(axis=1), atol=1e-7)
+    m.close()
