@@ -392,6 +392,27 @@ def main():
         plain = {"value": terms / sec_p, "ms_per_step": sec_p * 1e3, "max_rel_err": err_plain,
                  "meets_1e-4": bool(err_plain <= REL_TOL)}
 
+    # the FP32-VALU form beside it (frequency recurrence, compensated sums; the
+    # shape the sweeps found best on c1), priced against the FP32 vector peak
+    valu = None
+    if not args.no_plain:
+        Pv = torch.empty_like(Pn)
+
+        def run_valu():
+            lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pv, trig="recur", m=14, unroll=2,
+                                   sum="kahan", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
+
+        run_valu()
+        torch.cuda.synchronize()
+        err_v = sampled_error(curve, Pv.cpu().numpy())
+        sec_v = time_steps(run_valu, max(5, args.steps // 2), 2, on_start=lambda: lsp.lsp_profile_enable(True))
+        kv_ms, kv_n, kv_name = lsp.lsp_profile_read()
+        lsp.lsp_profile_enable(False)
+        kv_s = kv_ms / 1e3 / max(kv_n, 1)
+        valu = {"value": terms / sec_v, "ms_per_step": sec_v * 1e3, "kernel": kv_name, "kernel_avg_ms": kv_s * 1e3,
+                "frac_fp32_valu_peak": FLOP_PER_TERM * terms / kv_s / 1e12 / PEAK_FP32_TFLOPS,
+                "max_rel_err": err_v, "meets_1e-4": bool(err_v <= REL_TOL)}
+
     mfma = "mfma" in k_name
     flop = MFMA_FLOP_PER_TERM if mfma else FLOP_PER_TERM
     peak = PEAK_FP16_TFLOPS if mfma else PEAK_FP32_TFLOPS
@@ -416,6 +437,7 @@ def main():
         "max_rel_err": err_split,
         "meets_1e-4": bool(err_split <= REL_TOL),
         "plain": plain,
+        "valu_form": valu,
         "roofline": {
             "bound": "mfma" if mfma else "alu",
             "achieved": achieved,
