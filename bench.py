@@ -453,6 +453,11 @@ def main():
         },
         "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
     }
+    if args.config == "paper":
+        # the paper's own timing of this shape (Table 2: 20.3 s on a Tesla C1060, FP32,
+        # the V1449 Aql series this synthetic stand-in imitates); context only
+        line["paper_context"] = {"hardware": "Tesla C1060 (GT200)", "seconds": 20.3,
+                                 "terms_per_s": 382003 * 1528064 / 20.3, "speedup_here": 20.3 / sec}
     print(json.dumps(line), flush=True)
 
 
