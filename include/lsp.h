@@ -97,7 +97,7 @@ typedef enum lsp_sum_mode {
 typedef struct lsp_tile {
     int32_t trig;   /* lsp_trig_mode */
     int32_t m;      /* frequencies per lane: DIRECT 1,2,4; RECUR 4..24; MFMA 32 */
-    int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2 or 4 */
+    int32_t waves;  /* waves (64 lanes each) per workgroup: 1, 2 or 4 (MFMA also 8) */
     int32_t splits; /* workgroups sharing one frequency block along the sample
                        axis (1 = none); partials merged in fixed order in FP64 */
     int32_t unroll; /* samples per broadcast LDS read group: 1, 2 or 4 */

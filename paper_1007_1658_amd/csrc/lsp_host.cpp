@@ -219,12 +219,19 @@ lsp_tile default_tile(int phase, int64_t Nt, int64_t Nf, int cus)
         t.trig = LSP_TRIG_DIRECT;
         t.m = 1;
         t.sum = LSP_SUM_TWO;
+        t.unroll = 4;
+    } else if (phase == LSP_PHASE_SPLIT) {
+        // matrix-core form: FP16 hi/lo products with FP32 accumulation
+        t.trig = LSP_TRIG_MFMA;
+        t.m = 32;
+        t.sum = LSP_SUM_TWO;
+        t.unroll = 1;
     } else {
         t.trig = LSP_TRIG_RECUR;
         t.m = 8;
         t.sum = LSP_SUM_KAHAN;
+        t.unroll = 4;
     }
-    t.unroll = 4;
     t.waves = 4;
     t.splits = heuristic_splits(Nt, Nf, t.m, cus, t.waves, 0);
     return t;

@@ -231,7 +231,8 @@ static const Variant *find_variant(int phase, const lsp_tile &t)
 
 bool pgram_tile_supported(int phase, const lsp_tile &tile)
 {
-    if (tile.waves != 1 && tile.waves != 2 && tile.waves != 4) return false;
+    const bool eight = tile.trig == TR_MFMA && tile.waves == 8;  // matrix-core form: also 8 waves
+    if (tile.waves != 1 && tile.waves != 2 && tile.waves != 4 && !eight) return false;
     if (tile.splits < 1) return false;
     return find_variant(phase, tile) != nullptr;
 }

@@ -42,12 +42,14 @@ constexpr float kTrigScale = 16384.0f;  // 2^14
 
 enum { RR_H = 0, RR_L, RI_H, RI_L, R2R_H, R2R_L, R2I_H, R2I_L, R_KINDS };
 
+constexpr int kMfmaMaxWaves = 8;  // the matrix-core kernels take workgroups of up to 8 waves
+
 template <int NB, bool GLS>
 struct MfmaLds {
     double t[kMB];
     float x[kMB];
     float w[GLS ? kMB : 1];
-    float red[2][kMaxWaves];
+    float red[2][kMfmaMaxWaves];
     alignas(16) _Float16 R[R_KINDS][32 * NB][kMRow];  // 16-B rows: whole-row b128 reads and writes
 };
 
@@ -104,7 +106,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
     constexpr int NACC = GLS ? 6 : 4;
     __shared__ MfmaLds<NB, GLS> S;
     const int tid = threadIdx.x;
-    const int nw = blockDim.x / kWave;  // waves in the workgroup (1, 2 or 4)
+    const int nw = blockDim.x / kWave;  // waves in the workgroup (1 to 8)
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int half = lane >> 5;   // which 8 samples of a K-step this lane carries
@@ -271,7 +273,9 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
         }
 }
 
-__global__ void __launch_bounds__(256, 2) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }
+// 4- or 8-wave workgroups (an 8-wave group shares each block's R operands among
+// twice as many waves); 256 VGPRs at most either way, two waves per SIMD
+__global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }
 
 __global__ void __launch_bounds__(256, 2) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
 

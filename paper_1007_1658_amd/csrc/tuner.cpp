@@ -120,8 +120,10 @@ lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream, lsp
         // are the FP32 accumulators of its products, is a candidate)
         const int want_sum = (phase == LSP_PHASE_NAIVE) ? LSP_SUM_TWO : LSP_SUM_KAHAN;
         for (lsp_tile t : built)
-            for (int w : {2, 4}) {
+            for (int w : {2, 4, 8}) {
                 if (t.sum != want_sum && t.trig != LSP_TRIG_MFMA) continue;
+                if (w == 8 && t.trig != LSP_TRIG_MFMA) continue;  // 8 waves: matrix-core form only
+                if (w == 2 && t.trig == LSP_TRIG_MFMA) continue;  // too few waves to share R
                 t.waves = w;
                 int per_cu = 0;
                 t.splits = 1;
