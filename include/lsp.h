@@ -171,8 +171,8 @@ lsp_status lsp_periodogram_fast(const double *t, const float *x, int64_t Nt, dou
 
    t  device FP64 [Nt], y device FP32 [Nt], w device FP32 [Nt] weights >= 0
    (e.g. 1/sigma^2) or NULL for equal weights; Nt >= 3; grid as above;
-   p device FP32 [Nf] output, fully written.  waves: 0 (library's choice),
-   1, 2 or 4 per workgroup; splits: 0 (library's choice) or the number of
+   p device FP32 [Nf] output, fully written.  waves: 0 (library's choice,
+   8), 1, 2, 4 or 8 per workgroup; splits: 0 (library's choice) or the number of
    chunks of the sample axis.  All weights zero or a constant y give p = 0.
    Asynchronous on stream.  Errors: LSP_ERR_INVALID_ARG as above. */
 lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
@@ -188,7 +188,8 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
    the (2K x 2K) centred system is solved per frequency in FP64 by Cholesky,
    a column whose pivot falls to <= 1e-5 of its diagonal (or whose diagonal is
    <= 1e-5) being dropped.  K in {1, 2} (LSP_ERR_UNSUPPORTED above);
-   Nt >= 2K + 1; other arguments as lsp_gls. */
+   Nt >= 2K + 1; waves 0 (library's choice, 4), 1, 2 or 4 for K = 2; other
+   arguments as lsp_gls. */
 lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, int64_t Nt,
                              int32_t K, double f_min, double df, int64_t Nf, float *p,
                              int32_t waves, int32_t splits, void *stream);

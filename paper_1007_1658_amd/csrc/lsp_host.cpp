@@ -809,8 +809,8 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
         g_last_error = "invalid argument";
         return LSP_ERR_INVALID_ARG;
     }
-    if (waves != 0 && waves != 1 && waves != 2 && waves != 4) {
-        g_last_error = "waves must be 0 (library's choice), 1, 2 or 4";
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4 && !(K == 1 && waves == 8)) {
+        g_last_error = "waves must be 0 (library's choice), 1, 2 or 4 (generalized periodogram: also 8)";
         return LSP_ERR_INVALID_ARG;
     }
     if (splits < 0) {
@@ -823,7 +823,7 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     DeviceInfo *di = nullptr;
     lsp_status st = device_info(&dev, &di);
     if (st != LSP_OK) return st;
-    if (waves == 0) waves = 4;
+    if (waves == 0) waves = (K == 1) ? 8 : 4;  // GLS: 8 waves share each block's R operands
     if (splits == 0) splits = heuristic_splits(Nt, Nf, kGlsFreqPerWave / kWave, di->cus, waves, 2);
     int64_t chunk = 0;
     int eff = 1;

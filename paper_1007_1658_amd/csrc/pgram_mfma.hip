@@ -277,7 +277,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
 // twice as many waves); 256 VGPRs at most either way, two waves per SIMD
 __global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }
 
-__global__ void __launch_bounds__(256, 2) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
+__global__ void __launch_bounds__(512, 1) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
 
 // ---------------------------------------------------------------------------
 // Batched form: a persistent workgroup takes (curve, block of 4 x 32 a-rows =

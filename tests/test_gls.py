@@ -33,7 +33,7 @@ def _case(Nt, seed, weighted, offset=5.0):
 @pytest.mark.parametrize("Nt,Nf,splits", [(3, 7, 1), (5, 40, 1), (63, 100, 1), (64, 1025, 2), (130, 513, 3),
                                           (1000, 2000, 4), (4097, 3000, 7), (257, 8193, 1), (5000, 20, 64)])
 @pytest.mark.parametrize("weighted", [False, True])
-@pytest.mark.parametrize("waves", [4, 2])
+@pytest.mark.parametrize("waves", [8, 4, 2])
 def test_gls_matches_oracle(Nt, Nf, splits, weighted, waves):
     print(f"gls Nt={Nt} Nf={Nf} splits={splits} weighted={weighted} waves={waves}", flush=True)
     t, y, w = _case(Nt, 1, weighted)

@@ -70,6 +70,23 @@ def test_ragged_sizes(Nt, Nf, splits, phase, trig, m):
     assert peak_matches(Pg, P)
 
 
+@pytest.mark.parametrize("Nt,Nf,splits", [(3, 7, 1), (65, 513, 2), (1000, 511, 4), (4097, 30000, 5), (5000, 20, 64)])
+def test_matrix_core_form_eight_waves_ragged(Nt, Nf, splits):
+    """8-wave workgroups (the tuned matrix-core shape) on ragged sizes: partial
+    workgroups in frequency, ragged sample chunks."""
+    print(f"ragged mfma w8 Nt={Nt} Nf={Nf} splits={splits}", flush=True)
+    g = np.random.default_rng([12, Nt, Nf])
+    tt = np.sort(g.uniform(0.0, 30.0, Nt))
+    xx = (np.sin(2 * np.pi * 1.3 * tt) + g.normal(0, 1.0, Nt)).astype(np.float32)
+    df = 1.0 / (4 * (tt.max() - tt.min()))
+    c = synth.Curve(tt, xx, df, df, Nf)
+    P = oracle.periodogram(c.t, c.x, c.f_min, c.df, Nf=Nf)
+    t, x = to_dev(c)
+    Pg = lsp.lsp_periodogram_ex(t, x, c.f_min, c.df, Nf, trig="mfma", m=32, waves=8, splits=splits).cpu().numpy()
+    assert rel_err(Pg, P) <= REL_TOL
+    assert peak_matches(Pg, P)
+
+
 def test_default_call_and_output_fully_written(c0_case):
     c, P = c0_case
     t, x = to_dev(c)
@@ -121,7 +138,7 @@ def test_c2_precision_split_vs_naive():
 
 
 @pytest.mark.parametrize("config", ["c1", "c2"])
-@pytest.mark.parametrize("waves", [4, 2])
+@pytest.mark.parametrize("waves", [8, 4, 2])
 def test_matrix_core_form_full_size_sampled(config, waves):
     """The matrix-core form at full size (c1: small amplitudes; c2: epoch-offset
     times), oracle on sampled bins and around the peak."""
