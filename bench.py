@@ -29,6 +29,7 @@ PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz, packed 
 # double-angle sum), each 4 real products in three FP16 passes: 24 multiply-adds
 MFMA_FLOP_PER_TERM = 48
 PEAK_FP16_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
+PEAK_CLOCK_GHZ = 2.4        # the clock both published peaks assume
 REL_TOL = 1e-4
 
 WORKLOADS = {
@@ -62,9 +63,9 @@ def kernel_source_hash(kernel_name=""):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_name, workload):
-    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they
-    were taken on the current kernel source; else None."""
+def profile_entry(kernel_name, workload):
+    """The committed rocprofv3 PMC summary entry for this kernel and workload,
+    if it was taken on the current kernel source; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -74,9 +75,22 @@ def traffic_from_profiles(kernel_name, workload):
         e = d.get(f"{kernel_name}|{workload}")
         if not e or e.get("source_sha") != kernel_source_hash(kernel_name):
             return None
-        return float(e["bytes_per_launch"])
+        return e
     except Exception:
         return None
+
+
+def traffic_from_profiles(kernel_name, workload):
+    """HBM bytes per launch (PMC FETCH_SIZE/WRITE_SIZE, copy-calibrated), or None."""
+    e = profile_entry(kernel_name, workload)
+    return float(e["bytes_per_launch"]) if e and "bytes_per_launch" in e else None
+
+
+def clock_from_profiles(kernel_name, workload):
+    """Shader clock (GHz) during the kernel: GRBM_GUI_ACTIVE per XCD over the
+    kernel's average duration in the same profile, or None."""
+    e = profile_entry(kernel_name, workload)
+    return float(e["clock_ghz"]) if e and e.get("clock_ghz") else None
 
 
 def warm(fn, warmup, min_seconds=0.3):
@@ -418,6 +432,7 @@ def main():
     peak = PEAK_FP16_TFLOPS if mfma else PEAK_FP32_TFLOPS
     achieved = flop * terms / k_avg_s / 1e12
     traffic = traffic_from_profiles(k_name, args.config)
+    clock = clock_from_profiles(k_name, args.config)
     line = {
         "metric": METRIC,
         "value": value,
@@ -450,6 +465,9 @@ def main():
             "flop_per_term": flop,
             # the same kernel time priced as the FP32-vector form's 13 FLOP per term
             "fp32_valu_equiv_frac": FLOP_PER_TERM * terms / k_avg_s / 1e12 / PEAK_FP32_TFLOPS,
+            # the published peak assumes 2.4 GHz; the fraction at the clock the profile saw
+            "clock_ghz_profiled": clock,
+            "frac_at_profiled_clock": None if clock is None else achieved / (peak * clock / PEAK_CLOCK_GHZ),
         },
         "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
     }
