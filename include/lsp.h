@@ -141,7 +141,7 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt,
 /* Approximate periodogram by extirpolation and FFT (Press & Rybicki 1989,
    the approach Section 1 cites beside the direct sums), for comparison with
    the direct path: x - mean is spread onto a periodic grid of N points
-   (period 1/df, N = smallest power of two >= 4 macc (f_max/df + 1)) with
+   (period 1/df, N = smallest power of two >= 4 macc f_max/df) with
    the Lagrange weights of the macc nearest points, ones likewise at twice
    the positions; both grids are Fourier transformed (hipFFT, FP64) and
    Eq. (5) is evaluated on bins f_min/df .. f_min/df + Nf - 1.  Everything is

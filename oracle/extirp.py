@@ -21,8 +21,10 @@ import numpy as np
 
 
 def grid_size(k_max: int, macc: int) -> int:
-    """Smallest power of two >= 4 macc (k_max + 1)."""
-    need = 4 * macc * (int(k_max) + 1)
+    """Smallest power of two >= 4 macc k_max (k_max >= 1): 2 macc grid points
+    per period of the highest frequency the double-angle sums need, 2 k_max df,
+    as Press & Rybicki size the grid."""
+    need = 4 * macc * max(int(k_max), 1)
     n = 1
     while n < need:
         n <<= 1

@@ -4,6 +4,7 @@
 // and the launch sequence moments -> extirpolation -> FFT -> Eq. (5).
 #include <hipfft/hipfft.h>
 
+#include <algorithm>
 #include <cmath>
 #include <map>
 #include <mutex>
@@ -40,7 +41,7 @@ lsp_status fail(const char *what, hipError_t e)
 
 int64_t fast_grid_size(int64_t k_max, int macc)
 {
-    const int64_t need = 4 * (int64_t)macc * (k_max + 1);
+    const int64_t need = 4 * (int64_t)macc * std::max<int64_t>(k_max, 1);
     int64_t n = 1;
     while (n < need) n <<= 1;
     return n;
@@ -66,7 +67,7 @@ extern "C" lsp_status lsp_periodogram_fast(const double *t, const float *x, int6
     }
     const int64_t N = fast_grid_size(m0 + Nf - 1, macc);
     if (N > ((int64_t)1 << 28) || Nt > ((int64_t)1 << 31)) {
-        set_last_error("grid too large (4 macc (f_max / df + 1) > 2^28)");
+        set_last_error("grid too large (4 macc f_max / df > 2^28)");
         return LSP_ERR_INVALID_ARG;
     }
     if (lsp_device_count() < 1) return LSP_ERR_NO_DEVICE;
