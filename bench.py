@@ -133,11 +133,17 @@ def cpu_baseline(curve, target_s):
     import oracle
     cores = oracle.max_threads()
     g = np.random.default_rng(7)
-    k = np.sort(g.choice(curve.Nf, size=min(curve.Nf, 64), replace=False))
-    t0 = time.perf_counter()
-    oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
-    cal = max(time.perf_counter() - t0, 1e-3)
-    nb = int(min(curve.Nf, max(64, 64 * target_s / cal)))
+    # two calibration probes (the first, 64 frequencies, is dominated by start-up;
+    # the second is at most 16x larger), then the timed subset sized to target_s
+    nb = min(curve.Nf, 64)
+    for growth_cap in (16.0, None):
+        k = np.sort(g.choice(curve.Nf, size=nb, replace=False))
+        t0 = time.perf_counter()
+        oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
+        scale = target_s / max(time.perf_counter() - t0, 1e-3)
+        if growth_cap is not None:
+            scale = min(scale, growth_cap)
+        nb = int(min(curve.Nf, max(64, nb * scale)))
     k = np.sort(g.choice(curve.Nf, size=nb, replace=False))
     t0 = time.perf_counter()
     oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k)
