@@ -330,6 +330,9 @@ def main():
     ap.add_argument("--config", default="c1", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic launch shape")
+    ap.add_argument("--form", default="auto", choices=["auto", "valu"],
+                    help="auto: the library's (tuned) choice, the matrix-core form on MI355X; "
+                         "valu: time the FP32-VALU form (recurrence, compensated sums) instead")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batched-form", default="", choices=["", "mfma", "recur"],
@@ -382,8 +385,17 @@ def main():
         if args.save_tune:
             lsp.lsp_tune_cache_save(args.save_tune)
 
-    def run_split():
-        lsp.lsp_periodogram(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pn)
+    valu_kw = dict(trig="recur", m=14, unroll=2, sum="kahan", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
+    if args.form == "valu":
+        # the FP32-VALU form as the timed line (frequency recurrence, compensated sums)
+        tile = {"trig": lsp.LSP_TRIG_RECUR, "m": 14, "waves": 4, "splits": valu_kw["splits"], "unroll": 2,
+                "sum": lsp.LSP_SUM_KAHAN}
+
+        def run_split():
+            lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pn, **valu_kw)
+    else:
+        def run_split():
+            lsp.lsp_periodogram(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pn)
 
     # accuracy of the exact configuration that is timed
     run_split()
@@ -415,12 +427,11 @@ def main():
     # the FP32-VALU form beside it (frequency recurrence, compensated sums; the
     # shape the sweeps found best on c1), priced against the FP32 vector peak
     valu = None
-    if not args.no_plain:
+    if not args.no_plain and args.form != "valu":
         Pv = torch.empty_like(Pn)
 
         def run_valu():
-            lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pv, trig="recur", m=14, unroll=2,
-                                   sum="kahan", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
+            lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pv, **valu_kw)
 
         run_valu()
         torch.cuda.synchronize()
