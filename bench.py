@@ -351,8 +351,9 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the periodogram would shard by frequency; see the design notes)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path "
+              "(the periodogram would shard by frequency, each GPU taking Nf/G bins after a "
+              "broadcast of t and x)", file=sys.stderr)
         sys.exit(2)
 
     import torch
