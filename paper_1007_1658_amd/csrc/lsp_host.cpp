@@ -232,7 +232,9 @@ lsp_tile default_tile(int phase, int64_t Nt, int64_t Nf, int cus)
         t.sum = LSP_SUM_KAHAN;
         t.unroll = 4;
     }
-    t.waves = 4;
+    // matrix-core form: 8-wave groups (one per CU, sharing each block's R
+    // operands) from ~1e9 terms on; smaller problems want more, smaller groups
+    t.waves = (t.trig == LSP_TRIG_MFMA && (double)Nt * (double)Nf >= 1e9) ? 8 : 4;
     t.splits = heuristic_splits(Nt, Nf, t.m, cus, t.waves, 0);
     return t;
 }
@@ -272,7 +274,7 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
         if (tile.m == 0)
             tile.m = (tile.trig == d.trig) ? d.m
                                            : (tile.trig == LSP_TRIG_DIRECT ? 1 : (tile.trig == LSP_TRIG_MFMA ? 32 : 8));
-        if (tile.waves == 0) tile.waves = d.waves;
+        if (tile.waves == 0) tile.waves = (tile.trig == d.trig) ? d.waves : 4;
         if (tile.sum == 0 && tile.trig == d.trig && tile.m == d.m) tile.sum = d.sum;
         pgram_complete_tile(phase, tile);
     }
