@@ -187,9 +187,11 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
    sum w (y - Y) e^{i h wt} for h = 1..K: 3K complex matrix-core products;
    the (2K x 2K) centred system is solved per frequency in FP64 by Cholesky,
    a column whose pivot falls to <= 1e-5 of its diagonal (or whose diagonal is
-   <= 1e-5) being dropped.  K in {1, 2} (LSP_ERR_UNSUPPORTED above);
-   Nt >= 2K + 1; waves 0 (library's choice, 4), 1, 2 or 4 for K = 2; other
-   arguments as lsp_gls. */
+   <= 1e-5) being dropped.  K in 1..4 (LSP_ERR_UNSUPPORTED above; K = 3, 4
+   take two passes over the samples, six complex sums each at most);
+   Nt >= 2K + 1; waves 0 (library's choice, 4), 1, 2 or 4 for K >= 2; other
+   arguments as lsp_gls.  The workspace holds 6K floats per frequency and
+   sample chunk. */
 lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, int64_t Nt,
                              int32_t K, double f_min, double df, int64_t Nf, float *p,
                              int32_t waves, int32_t splits, void *stream);

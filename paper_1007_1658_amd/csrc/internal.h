@@ -136,7 +136,7 @@ hipError_t launch_prep_weighted(const double *t, const float *y, const float *w,
                                 int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s);
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // the multi-harmonic periodogram with K = 2 (pgram_mfma.hip): part[splits][12][Nf]
-hipError_t launch_mh(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
+hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;
 
 // moments and CurveStats only (no records)

@@ -783,7 +783,7 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt, doubl
     return h.zero_var ? LSP_ERR_ZERO_VARIANCE : LSP_OK;
 }
 
-// the generalized (K = 1) and multi-harmonic (K = 2) periodograms
+// the generalized (K = 1) and multi-harmonic (K = 2..4) periodograms
 static lsp_status run_weighted(const double *t, const float *y, const float *w, int64_t Nt, int K, double f_min,
                                double df, int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream);
 
@@ -796,8 +796,8 @@ lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt, 
 lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, int64_t Nt, int32_t K, double f_min,
                              double df, int64_t Nf, float *p, int32_t waves, int32_t splits, void *stream)
 {
-    if (K != 1 && K != 2) {
-        g_last_error = "harmonic count K must be 1 or 2";
+    if (K < 1 || K > 4) {
+        g_last_error = "harmonic count K must be 1 to 4";
         return K < 1 ? LSP_ERR_INVALID_ARG : LSP_ERR_UNSUPPORTED;
     }
     return run_weighted(t, y, w, Nt, K, f_min, df, Nf, p, waves, splits, stream);
@@ -876,7 +876,7 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
         ctx().prof_events.emplace_back(ev0, ev1);
         ctx().prof_name = (K == 1) ? "gls_mfma_kernel" : "mh_mfma_kernel";
     }
-    e = (K == 1) ? launch_gls(a, waves, s, ev0, ev1) : launch_mh(a, waves, s, ev0, ev1);
+    e = (K == 1) ? launch_gls(a, waves, s, ev0, ev1) : launch_mh(a, K, waves, s, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "generalized periodogram launch");
     return LSP_OK;
 }

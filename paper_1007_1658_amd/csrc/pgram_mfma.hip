@@ -254,9 +254,9 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
     // pads add 1 to Re of the second product, so CC gets the difference.
     const float uz = 1.0f / (kTrigScale * kTrigScale);
     const int64_t len = je - jb;
-    const int64_t p32 = (len + kMB - 1) / kMB * kMB - len;
-    const int64_t p64 = (len + kTile - 1) / kTile * kTile - len;
-    const float count = (float)(len - p32 + 2 * p64);
+    const int64_t pad_block = (len + kMB - 1) / kMB * kMB - len;     // pads of the last LDS block
+    const int64_t pad_tile = (len + kTile - 1) / kTile * kTile - len;  // pads the merge subtracts
+    const float count = (float)(len - pad_block + 2 * pad_tile);
 #pragma unroll
     for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -510,18 +510,41 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 //   C_m + i S_m = sum_j w_j e^{i m w t'_j}, m = 1..2K  (Gram entries through
 //   cos A cos B = (cos(A-B) + cos(A+B))/2 and the like), and
 //   YC_h + i YS_h = sum_j w_j (y_j - Y) e^{i h w t'_j}, h = 1..K,
-// i.e. 3K complex products of the same kind, with the R operands of
-// harmonics 1..2K.  K = 2 here: b range 32 (k = 32a + b), twelve 32x32 sums
-// per wave (one wave per SIMD), 16 operand kinds in LDS.
+// i.e. 3K complex products of the same kind, with the R operands of the
+// harmonics involved.  b range 32 (k = 32a + b); a wave holds at most six
+// complex sums (twelve 32x32 accumulators, one wave per SIMD), so K = 2 is one
+// pass over the samples and K = 3, 4 are two passes, each writing its own
+// slots of the per-chunk partial sums.
 
-constexpr int kMhK = 2;
+// One pass: weight sums of harmonics W0..W1 (none when W1 < W0) and value sums
+// of harmonics 1..V (none when V = 0).
+template <int W0, int W1, int V>
+struct MhPass {
+    static constexpr int NW = (W1 >= W0) ? W1 - W0 + 1 : 0;
+    static constexpr int NS = NW + V;
+    static constexpr int HMAX = (W1 > V) ? W1 : V;
+    static constexpr bool weight(int m) { return m >= W0 && m <= W1; }
+    static constexpr bool value(int m) { return m >= 1 && m <= V; }
+    static constexpr bool needed(int m) { return weight(m) || value(m); }
+    static constexpr int rslot(int m)
+    {
+        int r = 0;
+        for (int i = 1; i < m; ++i) r += needed(i) ? 1 : 0;
+        return r;
+    }
+    static constexpr int wslot(int m) { return m - W0; }      // accumulator of weight harmonic m
+    static constexpr int vslot(int h) { return NW + h - 1; }  // accumulator of value harmonic h
+    static constexpr int NR = rslot(HMAX + 1);                // harmonics with R operands in LDS
+    static_assert(NS >= 1 && NS <= 6, "a pass holds one to six complex sums");
+};
 
+template <int NR>
 struct MhLds {
     double t[kMB];
     float x[kMB];
     float w[kMB];
     float red[2][kMaxWaves];
-    alignas(16) _Float16 R[4 * 2 * kMhK][32][kMRow];  // harmonic m = 1..2K: (re hi, re lo, im hi, im lo)
+    alignas(16) _Float16 R[4 * NR][32][kMRow];  // per harmonic: (re hi, re lo, im hi, im lo)
 };
 
 // z = u v for complex u, v
@@ -531,11 +554,73 @@ __device__ __forceinline__ void cmul(float ur, float ui, float vr, float vi, flo
     zi = ur * vi + ui * vr;
 }
 
+// R operands of harmonic M for sample i of a group (e^{i M phi} from e^{i phi}
+// by repeated products), then the next harmonic
+template <class P, int M>
+struct MhRBuild {
+    __device__ __forceinline__ static void run(float c1, float s1, float cr, float ci, halfx8 (&v)[4 * P::NR], int i)
+    {
+        if constexpr (M > 1) cmul(cr, ci, c1, s1, cr, ci);
+        if constexpr (P::needed(M)) {
+            constexpr int r = P::rslot(M);
+            _Float16 h, l;
+            split16(cr * kTrigScale, h, l);
+            v[4 * r][i] = h;
+            v[4 * r + 1][i] = l;
+            split16(ci * kTrigScale, h, l);
+            v[4 * r + 2][i] = h;
+            v[4 * r + 3][i] = l;
+        }
+        if constexpr (M < P::HMAX) MhRBuild<P, M + 1>::run(c1, s1, cr, ci, v, i);
+    }
+};
+
+// the products of harmonic M over this lane's 8 samples, then the next harmonic
+template <class P, int M>
+struct MhStep {
+    __device__ __forceinline__ static void run(const float (&e1r)[8], const float (&e1i)[8], float (&er)[8],
+                                               float (&ei)[8], const float (&xv)[8], const float (&wv)[8],
+                                               const MhLds<P::NR> &S, int row, int js,
+                                               floatx16 (&acc)[P::NS][2])
+    {
+        if constexpr (M > 1) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) cmul(er[i], ei[i], e1r[i], e1i[i], er[i], ei[i]);
+        }
+        if constexpr (P::needed(M)) {
+            constexpr int r = P::rslot(M);
+            const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[4 * r][row][js]);
+            const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[4 * r + 1][row][js]);
+            const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[4 * r + 2][row][js]);
+            const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[4 * r + 3][row][js]);
+            if constexpr (P::weight(M)) {
+                constexpr int q = P::wslot(M);
+                COp LW;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) LW.set(i, wv[i] * er[i], wv[i] * ei[i]);
+                LSP_CMAC(LW, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
+            }
+            if constexpr (P::value(M)) {
+                constexpr int q = P::vslot(M);
+                COp LX;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) LX.set(i, xv[i] * er[i], xv[i] * ei[i]);
+                LSP_CMAC(LX, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
+            }
+        }
+        if constexpr (M < P::HMAX) MhStep<P, M + 1>::run(e1r, e1i, er, ei, xv, wv, S, row, js, acc);
+    }
+};
+
+// Per-chunk partial sums of one pass, written to the slots of the K-harmonic
+// layout: sum q (0..3K-1) = weight harmonic q + 1 for q < 2K, value harmonic
+// q - 2K + 1 after that; its real and imaginary parts at slots 2q and 2q + 1.
+template <int K, int W0, int W1, int V>
 __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 {
-    constexpr int M2 = 2 * kMhK;       // harmonics of the C, S sums
-    constexpr int NS = 3 * kMhK;       // complex sums: M2 of weights, kMhK of values
-    __shared__ MhLds S;
+    using P = MhPass<W0, W1, V>;
+    constexpr int NS = P::NS;
+    __shared__ MhLds<P::NR> S;
     const int tid = threadIdx.x;
     const int nw = blockDim.x / kWave;
     const int lane = tid & (kWave - 1);
@@ -573,7 +658,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
     const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
     const double Fa = a.f_min + (double)(a_row * 32) * a.df;
 
-    floatx16 acc[NS][2];  // [sum][re, im]: sums 0..M2-1 weights (m = 1..2K), M2.. values (h = 1..K)
+    floatx16 acc[NS][2];  // [sum][re, im], sums in the pass's order (weights, then values)
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         acc[q][0] = floatx16{};
@@ -590,33 +675,22 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
             S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
         }
         __syncthreads();
-        // R operands of harmonics 1..2K: 32 b x 8 groups of 8 samples
+        // R operands of the pass's harmonics: 32 b x 8 groups of 8 samples
         for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
             const int b = task / (kMB / 8);
             const int g = task % (kMB / 8);
             const double bdf = (double)b * a.df;
-            halfx8 v[4 * M2];
+            halfx8 v[4 * P::NR];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 double p = bdf * S.t[8 * g + i];
                 p -= rint(p);
                 const float ph = (float)p;
                 const float c1 = cos_rev(ph), s1 = sin_rev(ph);
-                float cr = c1, ci = s1;
-#pragma unroll
-                for (int m = 0; m < M2; ++m) {
-                    if (m > 0) cmul(cr, ci, c1, s1, cr, ci);
-                    _Float16 h, l;
-                    split16(cr * kTrigScale, h, l);
-                    v[4 * m][i] = h;
-                    v[4 * m + 1][i] = l;
-                    split16(ci * kTrigScale, h, l);
-                    v[4 * m + 2][i] = h;
-                    v[4 * m + 3][i] = l;
-                }
+                MhRBuild<P, 1>::run(c1, s1, c1, s1, v, i);
             }
 #pragma unroll
-            for (int q = 0; q < 4 * M2; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
+            for (int q = 0; q < 4 * P::NR; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
         }
         __syncthreads();
 #pragma unroll
@@ -635,27 +709,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
                 xv[i] = S.x[js + i];
                 wv[i] = S.w[js + i];
             }
-#pragma unroll
-            for (int m = 0; m < M2; ++m) {
-                if (m > 0) {
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) cmul(er[i], ei[i], e1r[i], e1i[i], er[i], ei[i]);
-                }
-                const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[4 * m][row][js]);
-                const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 1][row][js]);
-                const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 2][row][js]);
-                const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[4 * m + 3][row][js]);
-                COp LW;
-#pragma unroll
-                for (int i = 0; i < 8; ++i) LW.set(i, wv[i] * er[i], wv[i] * ei[i]);
-                LSP_CMAC(LW, rrh, rrl, rih, ril, acc[m][0], acc[m][1]);
-                if (m < kMhK) {
-                    COp LX;
-#pragma unroll
-                    for (int i = 0; i < 8; ++i) LX.set(i, xv[i] * er[i], xv[i] * ei[i]);
-                    LSP_CMAC(LX, rrh, rrl, rih, ril, acc[M2 + m][0], acc[M2 + m][1]);
-                }
-            }
+            MhStep<P, 1>::run(e1r, e1i, er, ei, xv, wv, S, row, js, acc);
         }
     }
 
@@ -666,12 +720,13 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
         const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
         const int64_t k = ar * 32 + row;
         if (k < a.Nf) {
-            float *p = a.part + (int64_t)split * 2 * NS * a.Nf + k;
+            float *p = a.part + (int64_t)split * 6 * K * a.Nf + k;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
-                const float u = (q < M2) ? uw : ux;
-                p[(2 * q) * a.Nf] = acc[q][0][r] * u;
-                p[(2 * q + 1) * a.Nf] = acc[q][1][r] * u;
+                const int gq = (q < P::NW) ? (W0 - 1 + q) : (2 * K + q - P::NW);
+                const float u = (q < P::NW) ? uw : ux;
+                p[(int64_t)(2 * gq) * a.Nf] = acc[q][0][r] * u;
+                p[(int64_t)(2 * gq + 1) * a.Nf] = acc[q][1][r] * u;
             }
         }
     }
@@ -681,13 +736,15 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 // h = 1..K, centred by their weighted means (the constant is fitted):
 //   G_ik = sum w u_i u_k - mean_i mean_k,  b_i = sum w (y - Y) u_i,
 // with sum w cos(Aw t) cos(Bw t) = (C_{A-B} + C_{A+B})/2 and the like
-// (C_0 = 1, S_0 = 0, C_{-m} = C_m, S_{-m} = -S_m).  Cholesky with column
-// dropping (a pivot <= 1e-5 of its diagonal, or a diagonal <= 1e-5: columns
-// the FP32 sums cannot separate); p = |L^{-1} b|^2 / YY.
+// (C_0 = 1, S_0 = 0, C_{-m} = C_m, S_{-m} = -S_m).  Cholesky (in place, lower
+// triangle) with column dropping (a pivot <= 1e-5 of its diagonal, or a
+// diagonal <= 1e-5: columns the FP32 sums cannot separate);
+// p = |L^{-1} b|^2 / YY.
+template <int K>
 __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
                                                         const CurveStats *__restrict__ st, float *__restrict__ P)
 {
-    constexpr int K = kMhK, M2 = 2 * kMhK, NS = 3 * kMhK, n = 2 * kMhK;
+    constexpr int M2 = 2 * K, NS = 3 * K, n = 2 * K;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= Nf) return;
     double v[2 * NS];
@@ -717,7 +774,7 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 #pragma unroll
     for (int i = 0; i < n; ++i)
 #pragma unroll
-        for (int j = 0; j < n; ++j) {
+        for (int j = 0; j <= i; ++j) {
             const int A = 1 + i / 2, B = 1 + j / 2;
             double raw;
             if (i % 2 == 0 && j % 2 == 0) raw = 0.5 * (Cm(A - B) + Cm(A + B));
@@ -727,55 +784,73 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
             G[i][j] = raw - mean[i] * mean[j];
         }
     const double eps = 1e-5;
-    double L[n][n], z[n];
-    bool keep[n];
+    double z[n];
     double explained = 0.0;
 #pragma unroll
     for (int i = 0; i < n; ++i) {
-        keep[i] = false;
+        // G[i][0..i-1] already hold L[i][0..i-1] (zero for dropped columns)
+        const double gii = G[i][i];
+        double d = gii;
+#pragma unroll
+        for (int c = 0; c < i; ++c) d -= G[i][c] * G[i][c];
         z[i] = 0.0;
+        if (!(gii > eps) || !(d > eps * gii)) {
 #pragma unroll
-        for (int c = 0; c < n; ++c) L[i][c] = 0.0;
-    }
-#pragma unroll
-    for (int i = 0; i < n; ++i) {
-        double d = G[i][i];
-#pragma unroll
-        for (int c = 0; c < i; ++c) d -= L[i][c] * L[i][c];
-        if (!(G[i][i] > eps) || !(d > eps * G[i][i])) continue;
-        keep[i] = true;
-        L[i][i] = sqrt(d);
+            for (int r = i + 1; r < n; ++r) G[r][i] = 0.0;  // column dropped
+            continue;
+        }
+        const double lii = sqrt(d);
 #pragma unroll
         for (int r = i + 1; r < n; ++r) {
             double t = G[r][i];
 #pragma unroll
-            for (int c = 0; c < i; ++c) t -= L[r][c] * L[i][c];
-            L[r][i] = t / L[i][i];
+            for (int c = 0; c < i; ++c) t -= G[r][c] * G[i][c];
+            G[r][i] = t / lii;
         }
         double t = b[i];
 #pragma unroll
-        for (int c = 0; c < i; ++c) t -= L[i][c] * z[c];
-        z[i] = t / L[i][i];
+        for (int c = 0; c < i; ++c) t -= G[i][c] * z[c];
+        z[i] = t / lii;
         explained += z[i] * z[i];
     }
-    (void)K;
     const double YY = st->var;
     P[k] = (YY > 0.0) ? (float)(explained / YY) : 0.0f;
 }
 
-hipError_t launch_mh(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+template <int K>
+static hipError_t launch_mh_k(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
     const int64_t per_wave = 32 * 32;
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + waves - 1) / waves;
+    const dim3 grid((unsigned)nblk, (unsigned)a.splits), block(kWave * waves);
     if (ev0) hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(mh_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
+    if constexpr (K == 2) {
+        hipLaunchKernelGGL((mh_mfma_kernel<2, 1, 4, 2>), grid, block, 0, s, a);
+    } else if constexpr (K == 3) {
+        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 6, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 0, 3>), grid, block, 0, s, a);
+    } else {
+        static_assert(K == 4, "K = 2, 3 or 4");
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 6, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 7, 8, 4>), grid, block, 0, s, a);
+    }
     if (ev1) hipEventRecord(ev1, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(mh_reduce_kernel, dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL((mh_reduce_kernel<K>), dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
                        (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn);
     return hipGetLastError();
+}
+
+hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
+{
+    switch (K) {
+    case 2: return launch_mh_k<2>(a, waves, s, ev0, ev1);
+    case 3: return launch_mh_k<3>(a, waves, s, ev0, ev1);
+    case 4: return launch_mh_k<4>(a, waves, s, ev0, ev1);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace lsp

@@ -118,6 +118,9 @@ def test_generalized_periodogram_validation_on_host():
         assert L.lsp_gls(*c, null) == lsp.LSP_ERR_INVALID_ARG, c
     # 8-wave workgroups: the generalized periodogram only (K = 1), not K = 2
     assert L.lsp_multiharmonic(fake, fake, null, 10, 2, 0.1, 0.1, 10, fake, 8, 0, null) == lsp.LSP_ERR_INVALID_ARG
+    # K beyond what is built; Nt below 2K + 1 for K = 4
+    assert L.lsp_multiharmonic(fake, fake, null, 20, 5, 0.1, 0.1, 10, fake, 0, 0, null) == lsp.LSP_ERR_UNSUPPORTED
+    assert L.lsp_multiharmonic(fake, fake, null, 8, 4, 0.1, 0.1, 10, fake, 0, 0, null) == lsp.LSP_ERR_INVALID_ARG
 
 
 def test_batched_validation_on_host():

@@ -1,4 +1,4 @@
-"""GPU parity of the multi-harmonic periodogram (K = 2) against the FP64 oracle
+"""GPU parity of the multi-harmonic periodogram (K = 2, 3, 4) against the FP64 oracle
 (the least-squares definition; Section 6.3's pointer to Schwarzenberg-Czerny).
 Bar: max|dp| / max(p_oracle) <= 1e-4 and the same peak bin."""
 import numpy as np
@@ -21,8 +21,8 @@ def _dev(*arrs):
     return [None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
 
 
-def _well_conditioned(t, w, fs, limit=1e3):
-    """Bins whose centred Gram matrix of (cos, sin)(h w t), h = 1, 2, has a
+def _well_conditioned(t, w, fs, limit=1e3, K=2):
+    """Bins whose centred Gram matrix of (cos, sin)(h w t), h = 1..K, has a
     condition number <= limit.  The GPU forms the normal equations from FP32
     sums, so its error grows with that number: below about half a cycle per
     baseline (the first bin or two of an oversampling-4 grid) the fit is
@@ -33,7 +33,7 @@ def _well_conditioned(t, w, fs, limit=1e3):
     ok = []
     for f in fs:
         th = 2 * np.pi * f * tc
-        U = np.stack([np.cos(th), np.sin(th), np.cos(2 * th), np.sin(2 * th)], 1)
+        U = np.stack([fn(h * th) for h in range(1, K + 1) for fn in (np.cos, np.sin)], 1)
         m = w @ U
         G = (U * w[:, None]).T @ U - np.outer(m, m)
         ok.append(np.linalg.cond(G) <= limit)
@@ -53,36 +53,41 @@ def _case(Nt, seed, weighted):
 @pytest.mark.parametrize("Nt,Nf,splits", [(9, 7, 1), (63, 100, 1), (64, 1025, 2), (130, 513, 3),
                                           (1000, 2000, 4), (4097, 3000, 7), (5000, 20, 64)])
 @pytest.mark.parametrize("weighted", [False, True])
-def test_multiharmonic_matches_oracle(Nt, Nf, splits, weighted):
-    print(f"mh Nt={Nt} Nf={Nf} splits={splits} weighted={weighted}", flush=True)
+@pytest.mark.parametrize("K", [2, 3, 4])
+def test_multiharmonic_matches_oracle(Nt, Nf, splits, weighted, K):
+    print(f"mh K={K} Nt={Nt} Nf={Nf} splits={splits} weighted={weighted}", flush=True)
+    if Nt < 2 * K + 3:
+        pytest.skip("as many samples as parameters: the fit interpolates and the Gram matrix is "
+                    "ill-conditioned at most bins")
     t, y, w = _case(Nt, 1, weighted)
     df = 1.0 / (4 * (t[-1] - t[0]))
-    P = oracle.multiharmonic(t, y.astype(np.float64), 2, df, df, Nf=Nf,
+    P = oracle.multiharmonic(t, y.astype(np.float64), K, df, df, Nf=Nf,
                              w=None if w is None else w.astype(np.float64))
     td, yd, wd = _dev(t, y, w)
-    Pg = lsp.lsp_multiharmonic(td, yd, 2, df, df, Nf, w=wd, splits=splits).cpu().numpy()
-    good = _well_conditioned(t, w, df + np.arange(Nf) * df)
+    Pg = lsp.lsp_multiharmonic(td, yd, K, df, df, Nf, w=wd, splits=splits).cpu().numpy()
+    good = _well_conditioned(t, w, df + np.arange(Nf) * df, K=K)
     assert good.mean() >= 0.7
     assert np.max(np.abs(Pg[good] - P[good])) <= REL_TOL * P.max()
     assert peak_matches(np.where(good, Pg, 0), np.where(good, P, 0))
     assert np.all(Pg >= -1e-5) and np.all(Pg <= 1 + 1e-5)
 
 
-def test_multiharmonic_full_size_sampled():
+@pytest.mark.parametrize("K", [2, 4])
+def test_multiharmonic_full_size_sampled(K):
     """c1's sampling (Nt 65,536, Nf 131,072) with weights; oracle on sampled bins."""
     c = synth.c1()
     g = np.random.default_rng(5)
     w = g.uniform(0.5, 2.0, c.Nt).astype(np.float32)
     td, yd, wd = _dev(c.t, c.x, w)
-    Pg = lsp.lsp_multiharmonic(td, yd, 2, c.f_min, c.df, c.Nf, w=wd).cpu().numpy()
+    Pg = lsp.lsp_multiharmonic(td, yd, K, c.f_min, c.df, c.Nf, w=wd).cpu().numpy()
     kpk = int(np.argmax(Pg))
     k = np.unique(np.concatenate([g.integers(0, c.Nf, 150), np.arange(max(0, kpk - 6), min(c.Nf, kpk + 7)),
                                   np.arange(0, 16), np.arange(c.Nf - 16, c.Nf)]))
-    P = oracle.multiharmonic(c.t, c.x.astype(np.float64), 2, c.f_min, c.df, k=k, w=w.astype(np.float64))
-    good = _well_conditioned(c.t, w, c.f_min + k * c.df)
+    P = oracle.multiharmonic(c.t, c.x.astype(np.float64), K, c.f_min, c.df, k=k, w=w.astype(np.float64))
+    good = _well_conditioned(c.t, w, c.f_min + k * c.df, K=K)
     assert good.mean() >= 0.95
     err = float(np.max(np.abs(Pg[k][good] - P[good])) / P.max())
-    print(f"mh c1 sampled rel err {err:.3e}", flush=True)
+    print(f"mh K={K} c1 sampled rel err {err:.3e}", flush=True)
     assert err <= REL_TOL
 
 
@@ -94,7 +99,7 @@ def test_one_harmonic_is_lsp_gls_and_bad_K_raises():
     pg = lsp.lsp_gls(td, yd, df, df, 1500, w=wd)
     assert torch.equal(p1, pg)
     with pytest.raises(lsp.LspError) as ei:
-        lsp.lsp_multiharmonic(td, yd, 3, df, df, 1500, w=wd)
+        lsp.lsp_multiharmonic(td, yd, 5, df, df, 1500, w=wd)
     assert ei.value.status == lsp.LSP_ERR_UNSUPPORTED
     with pytest.raises(lsp.LspError) as ei:
         lsp.lsp_multiharmonic(td, yd, 0, df, df, 1500, w=wd)

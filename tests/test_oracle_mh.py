@@ -21,7 +21,7 @@ def _lstsq_power(t, y, w, f, K):
     return 1.0 - chi2 / np.sum(w * (y - Y) ** 2)
 
 
-@pytest.mark.parametrize("K", [1, 2, 3])
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
 @pytest.mark.parametrize("weighted", [False, True])
 def test_mh_matches_brute_force_least_squares(K, weighted):
     g = np.random.default_rng([8, K, weighted])
