@@ -12,7 +12,7 @@
 namespace lsp {
 
 constexpr int kWave = 64;          // gfx950 wavefront width
-constexpr int kMaxWaves = 4;       // waves per workgroup supported by the kernels
+constexpr int kMaxWaves = 4;       // waves per workgroup of the VALU kernels (matrix-core ones: up to 8)
 constexpr int kTile = 64;          // samples staged per wave per tile (one per lane)
 constexpr int kFoldTiles = 8;      // tiles between compensated folds of the FP32 partials
 
