@@ -281,6 +281,7 @@ def run_gls(args):
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     terms = c.Nt * c.Nf
     flop = MH_FLOP_PER_HARMONIC * K if mh else GLS_FLOP_PER_TERM
+    clock = clock_from_profiles(k_name, args.config)
     achieved = flop * terms / k_avg_s / 1e12
     line = {
         "metric": (f"Nt·Nf terms/s of the multi-harmonic (K={K}) periodogram at max|Δp|≤1e-4" if mh else
@@ -290,8 +291,11 @@ def run_gls(args):
         "config": {"workload": WORKLOADS[args.config], "name": args.config, "Nt": c.Nt, "Nf": c.Nf},
         "max_rel_err": err, "meets_1e-4": bool(err <= REL_TOL),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP16_TFLOPS, "traffic": None, "kernel": k_name,
-                     "kernel_avg_ms": k_avg_s * 1e3, "flop_per_term": flop},
+                     "frac": achieved / PEAK_FP16_TFLOPS, "traffic": traffic_from_profiles(k_name, args.config),
+                     "kernel": k_name, "kernel_avg_ms": k_avg_s * 1e3, "flop_per_term": flop,
+                     "clock_ghz_profiled": clock,
+                     "frac_at_profiled_clock": None if clock is None else
+                     achieved / (PEAK_FP16_TFLOPS * clock / PEAK_CLOCK_GHZ)},
     }
     print(json.dumps(line), flush=True)
 
