@@ -25,6 +25,12 @@
  *    invariant to x -> a x + b and 0 <= Pn <= Nt/2.
  *  - Thread safety: calls may come from several host threads; each device
  *    and stream gets its own workspace, guarded by a mutex.
+ *  - Graph capture: a call may be captured on a stream (hipStreamBeginCapture,
+ *    torch.cuda.graph) once an uncaptured call of at least that size has set
+ *    up the stream's workspace (and, for lsp_periodogram_fast, its FFT plan);
+ *    a capture that would allocate returns LSP_ERR_CAPTURE.  A workspace a
+ *    capture used is never freed: when a later uncaptured call outgrows it,
+ *    it is kept aside (until the process ends) so the graph can still replay.
  */
 #ifndef MI355LSP_LSP_H
 #define MI355LSP_LSP_H

@@ -208,7 +208,7 @@ def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None
 
 def lsp_multiharmonic(t, y, K: int, f_min: float, df: float, Nf: int, w=None, p=None, waves=0, splits=0,
                       stream=None):
-    """Multi-harmonic periodogram p_K[Nf] (device float32), K in {1, 2}."""
+    """Multi-harmonic periodogram p_K[Nf] (device float32), K in 1..4."""
     torch = _torch()
     _dev_tensor(t, torch.float64, "t")
     _dev_tensor(y, torch.float32, "y")

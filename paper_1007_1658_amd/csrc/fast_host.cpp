@@ -10,6 +10,7 @@
 #include <mutex>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -21,6 +22,8 @@ struct FastState {
     // plans and workspaces per (device, stream, N)
     std::map<std::pair<int, hipStream_t>, std::map<int64_t, hipfftHandle>> plans;
     std::map<std::pair<int, hipStream_t>, std::pair<void *, size_t>> ws;
+    std::map<std::pair<int, hipStream_t>, bool> captured;  // a captured graph refers to ws
+    std::vector<void *> retired;                            // outgrown captured workspaces (never freed)
 };
 
 FastState &fs()
@@ -87,11 +90,24 @@ extern "C" lsp_status lsp_periodogram_fast(const double *t, const float *x, int6
     const size_t o_spec = o_grid + align256(sizeof(double) * 2 * (size_t)N);
     const size_t total = o_spec + align256(sizeof(double) * 4 * (size_t)(N / 2 + 1));
     auto &w = F.ws[key];
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(s, &cap) == hipSuccess && cap == hipStreamCaptureStatusActive;
+    if (capturing && (w.second < total || F.plans[key].find(N) == F.plans[key].end())) {
+        set_last_error("workspace or FFT plan would be created during stream capture (call once uncaptured first)");
+        return LSP_ERR_CAPTURE;
+    }
+    if (capturing) F.captured[key] = true;
     if (w.second < total) {
         if (w.first) {
             e = hipStreamSynchronize(s);
-            if (e == hipSuccess) e = hipFree(w.first);
             if (e != hipSuccess) return fail("workspace release", e);
+            if (F.captured[key]) {
+                F.retired.push_back(w.first);  // a captured graph may still replay into it
+            } else {
+                e = hipFree(w.first);
+                if (e != hipSuccess) return fail("workspace release", e);
+            }
+            F.captured[key] = false;
             w.first = nullptr;
             w.second = 0;
         }

@@ -42,6 +42,8 @@ struct DeviceInfo {
 struct Buffer {
     void *ptr = nullptr;
     size_t size = 0;
+    bool captured = false;       // a captured graph refers to ptr
+    std::vector<void *> retired;  // outgrown buffers a captured graph may still replay into (never freed)
 };
 
 struct BatchGraph {
@@ -117,22 +119,33 @@ bool stream_capturing(hipStream_t s)
     return st == hipStreamCaptureStatusActive;
 }
 
-// grow-only buffer; never grows while the stream is captured
+// Grow-only buffer.  It never grows while the stream is captured, and a buffer
+// that a capture used is retired, not freed, when a later eager call outgrows
+// it: the captured graph keeps replaying into it.
 lsp_status ensure(Buffer &b, size_t need, hipStream_t s)
 {
-    if (b.size >= need) return LSP_OK;
     if (stream_capturing(s)) {
-        g_last_error = "workspace would grow during stream capture";
-        return LSP_ERR_CAPTURE;
+        if (b.size < need) {
+            g_last_error = "workspace would grow during stream capture";
+            return LSP_ERR_CAPTURE;
+        }
+        b.captured = true;
+        return LSP_OK;
     }
+    if (b.size >= need) return LSP_OK;
     hipError_t e;
     if (b.ptr) {
         e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        e = hipFree(b.ptr);
-        if (e != hipSuccess) return hip_fail(e, "hipFree");
+        if (b.captured) {
+            b.retired.push_back(b.ptr);
+        } else {
+            e = hipFree(b.ptr);
+            if (e != hipSuccess) return hip_fail(e, "hipFree");
+        }
         b.ptr = nullptr;
         b.size = 0;
+        b.captured = false;
     }
     size_t sz = std::max(need, (size_t)1 << 20);
     e = hipMalloc(&b.ptr, sz);
