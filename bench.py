@@ -184,7 +184,14 @@ def microbench():
         for w in (1, 2, 4, 8):
             ops, ms = lsp.lsp_microbench(kind, w, 2048)
             res[f"{name}@{w}"] = ops
-    print(json.dumps({"microbench_lane_ops_per_s": res}), flush=True)
+    # matrix pipe alone and with 4 / 8 / 16 vector FMAs per MFMA, at 1 and 2 waves per
+    # SIMD (MFMA FLOP/s), and the 16-FMA stream alone (FMA/s)
+    co = {}
+    for w in (1, 2):
+        for kind, name in ((4, "mfma"), (5, "mfma+4fma"), (6, "mfma+8fma"), (7, "mfma+16fma"), (8, "16fma")):
+            ops, ms = lsp.lsp_microbench(kind, w, 1024)
+            co[f"{name}@{w}"] = {"ops_per_s": ops, "ms": ms}
+    print(json.dumps({"microbench_lane_ops_per_s": res, "mfma_coissue": co}), flush=True)
 
 
 def run_batched(args):

@@ -386,9 +386,12 @@ lsp_status lsp_tune_cache_load(const char *path);
    Measures one instruction class on the current device with eight
    independent chains per lane and `waves_per_simd` resident waves:
    kind 0 FP32 FMA, 1 FP64 FMA, 2 hardware sin+cos pair, 3 FP64 phase
-   reduction (multiply, round to nearest, subtract, convert to FP32).
-   Synchronous on `stream`.  *ops_per_s = lane-operations per second;
-   ms may be NULL. */
+   reduction (multiply, round to nearest, subtract, convert to FP32);
+   matrix-core / vector co-issue: kinds 4, 5, 6, 7 run four independent
+   32x32x16 FP16 MFMAs per step with 0, 4, 8, 16 independent FP32 FMAs after
+   each and report the MFMA FLOP rate; kind 8 runs kind 7's FMA stream alone
+   and reports FMAs per second.  Synchronous on `stream`.  *ops_per_s =
+   lane-operations (kinds 4-7: FLOPs) per second; ms may be NULL. */
 lsp_status lsp_microbench(int32_t kind, int32_t waves_per_simd, int32_t iters,
                           void *stream, double *ops_per_s, double *ms);
 

@@ -450,7 +450,8 @@ def lsp_tune_cache_load(path=None):
 
 
 def lsp_microbench(kind: int, waves_per_simd: int = 2, iters: int = 4096, stream=None):
-    """(lane-ops/s, ms) of one instruction class: 0 FP32 FMA, 1 FP64 FMA, 2 sin+cos, 3 FP64 phase."""
+    """(lane-ops/s, ms) of one instruction class: 0 FP32 FMA, 1 FP64 FMA, 2 sin+cos, 3 FP64 phase;
+    4-7 MFMA FLOP/s with 0, 4, 8, 16 FP32 FMAs per MFMA; 8 the 16-FMA stream alone (FMA/s)."""
     ops, ms = _D(), _D()
     _check(lib().lsp_microbench(int(kind), int(waves_per_simd), int(iters), _stream_ptr(stream),
                                 ctypes.byref(ops), ctypes.byref(ms)), "lsp_microbench")

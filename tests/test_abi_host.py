@@ -177,3 +177,12 @@ def test_fast_periodogram_validation_on_host():
     ]
     for c in cases:
         assert L.lsp_periodogram_fast(*c, null) == lsp.LSP_ERR_INVALID_ARG, c
+
+
+def test_microbench_validation_on_host():
+    L = lsp.lib()
+    ops = ctypes.c_double()
+    null = ctypes.c_void_p(0)
+    for kind, waves, iters in ((-1, 2, 10), (9, 2, 10), (4, 0, 10), (4, 9, 10), (4, 2, 0)):
+        assert L.lsp_microbench(kind, waves, iters, null, ctypes.byref(ops), None) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_microbench(4, 2, 10, null, None, None) == lsp.LSP_ERR_INVALID_ARG
