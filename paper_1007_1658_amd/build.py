@@ -52,7 +52,26 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    build_cli(verbose)
     return LIB
+
+
+CLI_SRC = os.path.join(PKG, "cli", "lsp_run.c")
+CLI = os.path.join(PKG, "cli", "lsp_run")
+
+
+def build_cli(verbose: bool = False) -> str:
+    """lsp_run: a plain C program on the C ABI (include/lsp.h compiled as C11)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = [os.environ.get("CC", "gcc"), "-O2", "-std=c11", "-Wall", "-Wextra", "-D__HIP_PLATFORM_AMD__",
+           "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(ROOT, "include"), CLI_SRC,
+           "-L" + PKG, "-lmi355lsp", "-L" + os.path.join(rocm, "lib"), "-lamdhip64",
+           "-Wl,-rpath,$ORIGIN/..", "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", CLI + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CLI + ".tmp", CLI)
+    return CLI
 
 
 if __name__ == "__main__":
