@@ -368,7 +368,7 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
 lsp_status lsp_autotune(int64_t Nt, int64_t Nf, int32_t phase, void *stream,
                         lsp_tile *best, double *best_ms);
 /* The launch shapes built into the library for a phase mode (waves and
-   splits are 0 in the listing: any of 1, 2, 4 waves and any split count work).
+   splits are 0 in the listing: 1, 2 or 4 waves, matrix-core shapes also 8, any split count).
    Writes at most cap entries to out (out may be NULL) and returns how many
    exist, or -1 for an unknown phase mode.  Host-only. */
 int32_t lsp_list_tiles(int32_t phase, lsp_tile *out, int32_t cap);

@@ -53,7 +53,46 @@ def build(verbose: bool = False) -> str:
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     build_cli(verbose)
+    build_host_check(verbose)
     return LIB
+
+
+HOST_SOURCES = ["lsp_host.cpp", "tuner.cpp", "surrogate.cpp", "fast_host.cpp"]
+CHECK_DIR = os.path.join(OUT_DIR, "host_check")
+CHECK = os.path.join(CHECK_DIR, "host_check")
+# host C++ only, built with the plain clang++ of ROCm (no HIP mode, no device code)
+SANITIZE = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined"]
+
+
+def build_host_check(verbose: bool = False) -> str:
+    """The host sources under AddressSanitizer/UBSan, linked with the device
+    objects of the main build and tests/host_check.cpp (validation paths and
+    file parsers, no GPU needed)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cxx = os.path.join(rocm, "llvm", "bin", "clang++")
+    os.makedirs(CHECK_DIR, exist_ok=True)
+    base = [cxx, "-x", "c++", "-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-Wno-unused-value",
+            "-I" + os.path.join(rocm, "include"), "-I" + os.path.join(ROOT, "include"), "-I" + CSRC] + SANITIZE
+    jobs = [(os.path.join(CSRC, f), os.path.join(CHECK_DIR, f + ".o")) for f in HOST_SOURCES]
+    jobs.append((os.path.join(ROOT, "tests", "host_check.cpp"), os.path.join(CHECK_DIR, "host_check.o")))
+
+    def one(job):
+        cmd = base + ["-c", job[0], "-o", job[1]]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return job[1]
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        objs = list(ex.map(one, jobs))
+    dev = [os.path.join(OUT_DIR, f + ".o") for f in SOURCES if f.endswith(".hip")]
+    cmd = [cxx] + SANITIZE + objs + dev + ["-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-lhipfft",
+                                           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", CHECK + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CHECK + ".tmp", CHECK)
+    return CHECK
 
 
 CLI_SRC = os.path.join(PKG, "cli", "lsp_run.c")

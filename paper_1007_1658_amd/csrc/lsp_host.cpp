@@ -694,7 +694,10 @@ extern "C" {
 
 const char *lsp_status_string(lsp_status s)
 {
-    switch (s) {
+    // a C caller may pass any int: read the bits, not the (range-limited) enum
+    int code = 0;
+    std::memcpy(&code, &s, sizeof(code) < sizeof(s) ? sizeof(code) : sizeof(s));
+    switch (code) {
     case LSP_OK: return "ok";
     case LSP_ERR_INVALID_ARG: return "invalid argument";
     case LSP_ERR_ZERO_VARIANCE: return "zero variance (constant series)";

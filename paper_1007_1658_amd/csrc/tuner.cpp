@@ -254,6 +254,10 @@ lsp_status lsp_tune_cache_load(const char *path)
             !num(ke, end, "splits", &sp) || !num(ke, end, "unroll", &un) || !num(ke, end, "sum", &su) ||
             !num(ke, end, "ms", &ms))
             return LSP_ERR_INVALID_ARG;
+        // every shape field a small non-negative integer (a foreign or damaged file is refused)
+        for (double v : {tr, m, w, sp, un, su})
+            if (!(v >= 0.0 && v <= 1048576.0) || v != std::floor(v)) return LSP_ERR_INVALID_ARG;
+        if (!std::isfinite(ms)) return LSP_ERR_INVALID_ARG;
         Entry e;
         e.tile.trig = (int32_t)tr;
         e.tile.m = (int32_t)m;
