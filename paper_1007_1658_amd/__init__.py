@@ -118,6 +118,17 @@ SIGNATURES = {
 }
 
 
+def load_library(path):
+    """A libmi355lsp build at `path` with the C signatures declared (e.g. the
+    LDS-poisoning debug build, debug/libmi355lsp_poison.so)."""
+    L = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    return L
+
+
 def lib():
     """The loaded libmi355lsp.so (raises if it has not been built)."""
     global _lib
@@ -125,12 +136,7 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                               "(or python paper_1007_1658_amd/build.py)")
-        L = ctypes.CDLL(LIB_PATH)
-        for name, (res, args) in SIGNATURES.items():
-            fn = getattr(L, name)
-            fn.restype = res
-            fn.argtypes = args
-        _lib = L
+        _lib = load_library(LIB_PATH)
     return _lib
 
 

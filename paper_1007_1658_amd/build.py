@@ -28,10 +28,10 @@ DEVICE = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
+def _compile(src: str, verbose: bool, defines=()) -> str:
     os.makedirs(OUT_DIR, exist_ok=True)
-    obj = os.path.join(OUT_DIR, src + ".o")
-    cmd = [HIPCC] + COMMON + DEVICE
+    obj = os.path.join(OUT_DIR, src + (".poison" if defines else "") + ".o")
+    cmd = [HIPCC] + COMMON + DEVICE + list(defines)
     if src.endswith(".hip"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -44,14 +44,28 @@ def _compile(src: str, verbose: bool) -> str:
     return obj
 
 
+POISON_SRC = "pgram_mfma.hip"   # the kernels whose waves share LDS operands across barriers
+POISON_LIB = os.path.join(PKG, "debug", "libmi355lsp_poison.so")
+
+
 def build(verbose: bool = False) -> str:
-    with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
-    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs + ["-lhipfft"]
+    jobs = [(s, ()) for s in SOURCES] + [(POISON_SRC, ("-DLSP_POISON_LDS",))]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=len(jobs)) as ex:
+        objs = list(ex.map(lambda j: _compile(j[0], verbose, j[1]), jobs))
+    main_objs, poison_obj = objs[:len(SOURCES)], objs[len(SOURCES)]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", LIB + ".tmp"] + main_objs + ["-lhipfft"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
+    # debug variant: shared LDS operands poisoned with NaN between blocks (race check)
+    os.makedirs(os.path.dirname(POISON_LIB), exist_ok=True)
+    pobjs = [poison_obj if s == POISON_SRC else o for s, o in zip(SOURCES, main_objs)]
+    cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", POISON_LIB + ".tmp"] + pobjs + ["-lhipfft"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(POISON_LIB + ".tmp", POISON_LIB)
     build_cli(verbose)
     build_host_check(verbose)
     return LIB

@@ -59,6 +59,22 @@ __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
     lo = (_Float16)(v - (float)hi);
 }
 
+// Debug build (LSP_POISON_LDS): once a block's shared operands have been
+// consumed, every byte of the staging area is set to NaN bits before the next
+// block is written, so a read that no barrier orders after its write yields
+// NaN and fails the parity tests.  A no-op in the normal build.
+template <class T>
+__device__ __forceinline__ void lds_poison(T &s)
+{
+#ifdef LSP_POISON_LDS
+    uint32_t *p = reinterpret_cast<uint32_t *>(&s);
+    for (int i = threadIdx.x; i < (int)(sizeof(T) / 4); i += blockDim.x) p[i] = 0xffffffffu;
+    __syncthreads();
+#else
+    (void)s;
+#endif
+}
+
 __device__ __forceinline__ float wave_max(float v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
@@ -151,6 +167,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
 
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();  // the previous block's LDS is consumed
+        lds_poison(S);
         if (tid < kMB) {
             const int64_t j = j0 + tid;
             const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0 (GLS: w = 0)
@@ -351,6 +368,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
 
         for (int64_t j0 = 0; j0 < Nt; j0 += kMB) {
             __syncthreads();
+            lds_poison(S);
             if (tid < kMB) {
                 const int64_t j = j0 + tid;
                 const bool ok = j < Nt;
@@ -667,6 +685,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();
+        lds_poison(S);
         if (tid < kMB) {
             const int64_t j = j0 + tid;
             const bool ok = j < je;  // ragged end: t' = 0, x = 0, w = 0 (adds nothing)
