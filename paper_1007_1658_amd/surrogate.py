@@ -23,7 +23,7 @@ from . import Model, lsp_fap_analytic, lsp_mc_maxpower, lsp_window_features
 from . import synth
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_MODEL = os.path.join(_HERE, "models", "fap_surrogate_gfx950.bin")
+DEFAULT_MODEL = os.path.join(_HERE, "fap_model", "fap_surrogate_gfx950.bin")
 FAP_LEVELS = (0.001, 0.01, 0.05, 0.1)
 
 
