@@ -315,8 +315,17 @@ lsp_status lsp_model_set_scalers(lsp_model *m, const float *feat_mean, const flo
    equal lsp_model_param_count()). */
 lsp_status lsp_model_get_params(const lsp_model *m, int32_t member, float *host, int64_t n);
 lsp_status lsp_model_set_params(lsp_model *m, int32_t member, const float *host, int64_t n);
-/* Binary model file (little-endian): header, scalers, per member the step
-   count and the weights, plus the Adam moments when with_optimizer != 0.
+/* Calibrated error of the surrogate's mean FAP: rms[7] (host FP32, each in
+   [0, 1]) is the RMS error, measured against Monte Carlo on patterns kept out
+   of training, in the bins of the FAP itself with upper edges 0.002, 0.005,
+   0.02, 0.05, 0.2, 0.5 (the last bin ends at 1).  lsp_fap_surrogate reports
+   fap_sigma = sqrt(members' spread^2 + rms(bin of fap)^2) and falls back to
+   Monte Carlo where that exceeds max_sigma.  All zeros (the default) leave the
+   members' spread alone.  LSP_ERR_INVALID_ARG unless n == 7. */
+lsp_status lsp_model_set_error_table(lsp_model *m, const float *rms, int32_t n);
+/* Binary model file (little-endian): header (version 2), scalers, the error
+   table, per member the step count and the weights, plus the Adam moments
+   when with_optimizer != 0 (version-1 files, without the table, still load).
    Load reports LSP_ERR_MODEL for a missing, truncated or mismatched file. */
 lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_optimizer);
 lsp_status lsp_model_load(const char *path, lsp_model **out);

@@ -88,6 +88,7 @@ SIGNATURES = {
     "lsp_model_get_params": (_I32, [_P, _I32, _P, _I64]),
     "lsp_model_set_params": (_I32, [_P, _I32, _P, _I64]),
     "lsp_model_save": (_I32, [_P, ctypes.c_char_p, _I32]),
+    "lsp_model_set_error_table": (_I32, [_P, _P, _I32]),
     "lsp_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "lsp_mlp_forward": (_I32, [_P, _P, _I32, _P, _P]),
     "lsp_mlp_grad": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _P]),
@@ -550,6 +551,15 @@ class Model:
         _check(lib().lsp_model_set_scalers(self.h, m.ctypes.data_as(ctypes.c_void_p),
                                            sd.ctypes.data_as(ctypes.c_void_p), float(feat_zmax), float(q_mu),
                                            float(q_sigma)), "lsp_model_set_scalers")
+
+    # upper edges of the FAP bins of the calibrated error table (last bin ends at 1)
+    ERR_EDGES = (0.002, 0.005, 0.02, 0.05, 0.2, 0.5)
+
+    def set_error_table(self, rms):
+        """RMS error of the mean FAP per FAP bin (7 values; edges in ERR_EDGES)."""
+        a = np.ascontiguousarray(np.asarray(rms, dtype=np.float32))
+        _check(lib().lsp_model_set_error_table(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size),
+               "lsp_model_set_error_table")
 
     def save(self, path: str, with_optimizer: bool = False):
         _check(lib().lsp_model_save(self.h, path.encode(), 1 if with_optimizer else 0), "lsp_model_save")

@@ -12,6 +12,7 @@ constexpr int kMlpHidden = 256;
 constexpr int kMlpOut = 2;        // location and scale of the law of the maximum
 constexpr int kMlpOutPad = 32;    // padded to the 32-wide output tile
 constexpr int kMlpLayers = 4;
+constexpr int kErrBins = 7;      // FAP bins of the calibrated error table
 constexpr int kQuantiles = 9;     // reported quantile levels (see quantile_level)
 constexpr int kFeatLogNt = 64;    // raw feature slots holding log10 Nt and log10 Nf
 constexpr int kFeatLogNf = 67;

@@ -43,6 +43,16 @@ constexpr int64_t kParams = 256 * 68 + 256 + 2 * (65536 + 256) + kMlpOut * 256 +
 
 size_t round32(size_t v) { return (v + 31) / 32 * 32; }
 
+// upper edges of the FAP bins of the calibrated error table (the last bin ends at 1)
+constexpr float kErrEdges[kErrBins - 1] = {0.002f, 0.005f, 0.02f, 0.05f, 0.2f, 0.5f};
+
+float err_of(const float *rms, float fap)
+{
+    int b = 0;
+    while (b < kErrBins - 1 && !(fap < kErrEdges[b])) ++b;
+    return rms[b];
+}
+
 }  // namespace
 }  // namespace lsp
 
@@ -55,6 +65,7 @@ struct lsp_model {
     float feat_std[kMlpIn];
     float feat_zmax = 1e30f;  // patterns whose standardized features exceed this fall back to Monte Carlo
     float q_mu = 0.f, q_sigma = 1.f;
+    float err_rms[kErrBins] = {};  // calibrated RMS error of the mean FAP per bin of the FAP itself
     std::vector<float *> P, G, M1, M2;
     std::vector<int> step;
     std::vector<std::array<__bf16 *, kMlpLayers>> Wb, WbT;
@@ -426,12 +437,21 @@ lsp_status lsp_mlp_adam_step(lsp_model *m, int32_t member, float lr, float beta1
     return e == hipSuccess ? LSP_OK : fail(e, "lsp_mlp_adam_step");
 }
 
+lsp_status lsp_model_set_error_table(lsp_model *m, const float *rms, int32_t n)
+{
+    if (!good_model(m) || !rms || n != kErrBins) return LSP_ERR_INVALID_ARG;
+    for (int32_t i = 0; i < n; ++i)
+        if (!(rms[i] >= 0.f && rms[i] <= 1.f)) return LSP_ERR_INVALID_ARG;
+    std::memcpy(m->err_rms, rms, sizeof(m->err_rms));
+    return LSP_OK;
+}
+
 lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_optimizer)
 {
     if (!good_model(m) || !path) return LSP_ERR_INVALID_ARG;
     std::ofstream f(path, std::ios::binary);
     if (!f) return LSP_ERR_INVALID_ARG;
-    const int32_t hdr[8] = {1, m->members, kMlpIn, kMlpInPad, kMlpHidden, kMlpOut, kMlpOutPad, with_optimizer ? 1 : 0};
+    const int32_t hdr[8] = {2, m->members, kMlpIn, kMlpInPad, kMlpHidden, kMlpOut, kMlpOutPad, with_optimizer ? 1 : 0};
     f.write(kMagic, 16);
     f.write((const char *)hdr, sizeof(hdr));
     f.write((const char *)&m->seed, 8);
@@ -439,6 +459,7 @@ lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_opt
     f.write((const char *)m->feat_std, sizeof(m->feat_std));
     const float sc[3] = {m->feat_zmax, m->q_mu, m->q_sigma};
     f.write((const char *)sc, sizeof(sc));
+    f.write((const char *)m->err_rms, sizeof(m->err_rms));  // version 2
     std::vector<float> h(kPadded);
     for (int e = 0; e < m->members; ++e) {
         const int32_t st = m->step[e];
@@ -467,7 +488,8 @@ lsp_status lsp_model_load(const char *path, lsp_model **out)
     int32_t hdr[8];
     f.read(magic, 16);
     f.read((char *)hdr, sizeof(hdr));
-    if (!f || std::memcmp(magic, kMagic, 16) != 0 || hdr[0] != 1 || hdr[2] != kMlpIn || hdr[3] != kMlpInPad ||
+    if (!f || std::memcmp(magic, kMagic, 16) != 0 || (hdr[0] != 1 && hdr[0] != 2) || hdr[2] != kMlpIn ||
+        hdr[3] != kMlpInPad ||
         hdr[4] != kMlpHidden || hdr[5] != kMlpOut || hdr[6] != kMlpOutPad || hdr[1] < 1 || hdr[1] > 16) {
         set_last_error("model file header mismatch");
         return LSP_ERR_MODEL;
@@ -483,6 +505,15 @@ lsp_status lsp_model_load(const char *path, lsp_model **out)
     m->feat_zmax = sc[0];
     m->q_mu = sc[1];
     m->q_sigma = sc[2];
+    if (hdr[0] >= 2) {  // calibrated error table
+        f.read((char *)m->err_rms, sizeof(m->err_rms));
+        for (float v : m->err_rms)
+            if (!(v >= 0.f && v <= 1.f)) {
+                lsp_model_destroy(m);
+                set_last_error("model file: bad error table");
+                return LSP_ERR_MODEL;
+            }
+    }
     std::vector<float> h(kPadded);
     for (int e = 0; e < m->members && f; ++e) {
         int32_t stp = 0;
@@ -544,7 +575,7 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
     if (he != hipSuccess) return fail(he, "feature buffer");
     lsp_status st = lsp_window_features(t, off, n_pat, f_min, df, Nf, feat, stream);
     // 2. the law from every member, 3. FAP and its spread
-    std::vector<float> hz((size_t)n_pat), hs((size_t)n_pat);
+    std::vector<float> hz((size_t)n_pat), hs((size_t)n_pat), hf((size_t)n_pat);
     if (st == LSP_OK) {
         std::lock_guard<std::mutex> lock(m->mu);
         const int Bp = (int)round32((size_t)n_pat);
@@ -560,7 +591,18 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
         if (he == hipSuccess) he = hipMemcpyAsync(hz.data(), m->zmax, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
         if (he == hipSuccess)
             he = hipMemcpyAsync(hs.data(), fap_sigma, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess) he = hipMemcpyAsync(hf.data(), fap, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
         if (he == hipSuccess) he = hipStreamSynchronize(s);
+        // predicted uncertainty: the members' spread and the calibrated error of the
+        // mean FAP at this FAP, in quadrature
+        if (he == hipSuccess) {
+            for (int32_t p = 0; p < n_pat; ++p) {
+                const float ce = err_of(m->err_rms, hf[p]);
+                hs[p] = std::sqrt(hs[p] * hs[p] + ce * ce);
+            }
+            he = hipMemcpyAsync(fap_sigma, hs.data(), sizeof(float) * n_pat, hipMemcpyHostToDevice, s);
+            if (he == hipSuccess) he = hipStreamSynchronize(s);
+        }
     }
     hipFree(feat);
     if (st != LSP_OK) return st;

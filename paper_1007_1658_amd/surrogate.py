@@ -125,6 +125,38 @@ def train(F, Y, members=4, steps=1500, batch=256, lr=2e-3, seed=0, holdout=0.1, 
     return model, history
 
 
+CAL_LEVELS = (0.001, 0.003, 0.01, 0.03, 0.1, 0.3, 0.6)   # one or more per bin of the error table
+
+
+def calibrate(model, b: synth.Batch, R=10000, seed=30300, levels=CAL_LEVELS):
+    """The error table lsp_fap_surrogate adds to the members' spread: per bin of
+    the predicted FAP (edges Model.ERR_EDGES), the RMS of (FAP_net - FAP_MC) on
+    patterns kept out of training and validation, with the Monte Carlo's own
+    variance FAP (1 - FAP) / R removed.  Returns (rms[7], counts[7])."""
+    torch = _torch()
+    td = _device_t(b)
+    Y = monte_carlo(b, R, seed)
+    Ys, _ = torch.sort(Y, dim=1)
+    edges32 = np.array(Model.ERR_EDGES, dtype=np.float32)   # binned in float32, as the library does
+    nb = len(edges32) + 1
+    sq, noise, cnt = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    for a in levels:
+        k = max(0, int(math.ceil((1.0 - a) * R)) - 1)
+        p_obs = Ys[:, k].contiguous()
+        fap_mc = (Y >= p_obs[:, None]).double().mean(dim=1).cpu().numpy()
+        f, _, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=1e9, mc_realizations=0)
+        f32 = f.cpu().numpy()
+        bins = np.searchsorted(edges32, f32, side="right")
+        f = f32.astype(np.float64)
+        np.add.at(sq, bins, (f - fap_mc) ** 2)
+        np.add.at(noise, bins, fap_mc * (1.0 - fap_mc) / R)
+        np.add.at(cnt, bins, 1.0)
+    rms = np.sqrt(np.maximum(0.0, (sq - noise) / np.maximum(cnt, 1.0)))
+    if (cnt > 0).any():
+        rms[cnt == 0] = rms[cnt > 0].max()   # unseen bins: the largest measured error
+    return rms.astype(np.float32), cnt.astype(np.int64)
+
+
 def validate(model, b: synth.Batch, R=10000, seed=20260, levels=FAP_LEVELS, max_sigma=0.005, log=None):
     """|FAP_surrogate - FAP_MC| at the MC quantiles for the given FAP levels, the
     same for Eq. (3), the fallback rate and the speed against Monte Carlo."""
@@ -177,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--val-patterns", type=int, default=200)
     ap.add_argument("--R", type=int, default=500)
     ap.add_argument("--R-val", type=int, default=10000)
+    ap.add_argument("--cal-patterns", type=int, default=200,
+                    help="patterns (an independent draw) for the error table; 0 = no table")
     ap.add_argument("--members", type=int, default=4)
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=256)
@@ -204,10 +238,21 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"trained in {t_train:.1f} s")
+    cal_info = None
+    if args.cal_patterns > 0:
+        cal = synth.c4_patterns(args.cal_patterns, seed_sub=1, nt_range=(200, args.nt_max))
+        t0 = time.perf_counter()
+        rms, cnt = calibrate(model, cal, R=args.R_val)
+        model.set_error_table(rms)
+        cal_info = {"patterns": cal.n, "R": args.R_val, "edges": list(Model.ERR_EDGES),
+                    "rms": [float(v) for v in rms], "counts": [int(v) for v in cnt],
+                    "seconds": time.perf_counter() - t0}
+        log(f"error table {np.round(rms, 4).tolist()} (counts {cnt.tolist()})")
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         model.save(args.out)
     res = validate(model, va, R=args.R_val, log=log)
+    res["error_table"] = cal_info
     res.update({"train_patterns": tr.n, "R_train": args.R, "data_seconds": t_data, "train_seconds": t_train,
                 "members": args.members, "steps": args.steps, "early_stopping": hist})
     log(json.dumps(res))

@@ -228,3 +228,39 @@ def test_out_of_range_features_route_to_monte_carlo():
     pm = lsp.lsp_mc_maxpower(td, off, fm, df, nf, 64, seed=5).cpu().numpy()
     assert np.allclose(fap.cpu().numpy(), (pm >= 8.0).mean(axis=1), atol=1e-7)
     m.close()
+
+
+def test_error_table_enters_sigma_fallback_and_model_file(tmp_path):
+    """fap_sigma = sqrt(spread^2 + rms(bin of fap)^2); the table decides the
+    fallback and survives save/load."""
+    t, off, fm, df, nf = _patterns(12, 6)
+    td = torch.from_numpy(t).cuda()
+    feat = lsp.lsp_window_features(td, off, fm, df, nf)
+    F = feat.cpu().numpy()
+    m = lsp.Model(members=3, seed=7)
+    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, -0.4, 0.5)
+    p_obs = torch.full((12,), 7.0, device="cuda")
+    f0, s0, u0 = m.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
+    rms = np.array([0.001, 0.002, 0.003, 0.004, 0.006, 0.008, 0.01], dtype=np.float32)
+    m.set_error_table(rms)
+    f1, s1, _ = m.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
+    f0, s0, f1, s1 = (a.cpu().numpy().astype(np.float64) for a in (f0, s0, f1, s1))
+    assert np.array_equal(f0, f1)
+    # bin b holds FAP below edge b (float32 comparisons, as in the library)
+    edges32 = np.array(lsp.Model.ERR_EDGES, dtype=np.float32)
+    f32 = f1.astype(np.float32)
+    bins = np.array([next((i for i, e in enumerate(edges32) if v < e), 6) for v in f32])
+    tab = rms[bins].astype(np.float64)
+    assert np.allclose(s1, np.sqrt(s0 ** 2 + tab ** 2), rtol=1e-5, atol=1e-9)
+    # a threshold below every table entry sends every pattern to Monte Carlo
+    _, _, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=0.0005, mc_realizations=32, seed=3)
+    assert used.sum().item() == 12
+    path = str(tmp_path / "m.bin")
+    m.save(path)
+    m2 = lsp.Model(path=path)
+    _, s2, _ = m2.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
+    assert np.allclose(s2.cpu().numpy(), s1, rtol=1e-6)
+    with pytest.raises(lsp.LspError) as ei:
+        m.set_error_table(np.zeros(5, dtype=np.float32))
+    assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
+    m.close(); m2.close()
