@@ -59,6 +59,31 @@ __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
     lo = (_Float16)(v - (float)hi);
 }
 
+// the same for a v that is not a product: lo = fp16(v * one - hi) with `one`
+// equal to 1 but opaque to the compiler (held in a register), which then emits
+// one mixed-precision multiply-add instead of a conversion and a subtraction
+__device__ __forceinline__ void split16_sum(float v, float one, _Float16 &hi, _Float16 &lo)
+{
+    hi = (_Float16)v;
+    lo = (_Float16)fmaf(v, one, -(float)hi);
+}
+
+__device__ __forceinline__ float opaque_one()
+{
+    float one = 1.0f;
+    asm volatile("" : "+v"(one));
+    return one;
+}
+
+// g e^{2i theta} from c = cos theta, s = sin theta: cos 2theta = 2c^2 - 1 and
+// sin 2theta = 2cs, as one product, one fused multiply-add and one product
+__device__ __forceinline__ void double_angle(float c, float s, float g, float &c2g, float &s2g)
+{
+    const float t = c * (2.0f * g);
+    c2g = fmaf(t, c, -g);
+    s2g = t * s;
+}
+
 // Debug build (LSP_POISON_LDS): once a block's shared operands have been
 // consumed, every byte of the staging area is set to NaN bits before the next
 // block is written, so a read that no barrier orders after its write yields
@@ -81,7 +106,15 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
-// the complex operand v = (re, im) as hi/lo FP16 halves, plus -im for the real part
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ halfx8 neg8(halfx8 v)
+{
+    return __builtin_bit_cast(halfx8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u);
+}
+
+// the complex operand v = (re, im) as hi/lo FP16 halves, plus -im for the real
+// part (filled by set() for each of the 8 samples, then finish())
 struct COp {
     halfx8 rh, rl, ih, il, nih, nil;
     __device__ __forceinline__ void set(int i, float re, float im)
@@ -93,8 +126,23 @@ struct COp {
         split16(im, h, l);
         ih[i] = h;
         il[i] = l;
-        nih[i] = -h;
-        nil[i] = -l;
+    }
+    // -im from im, a sign flip of both halves of each 32-bit word
+    __device__ __forceinline__ void finish()
+    {
+        nih = neg8(ih);
+        nil = neg8(il);
+    }
+    // set() with re not a product (see split16_sum)
+    __device__ __forceinline__ void set_sum(int i, float re, float im, float one)
+    {
+        _Float16 h, l;
+        split16_sum(re, one, h, l);
+        rh[i] = h;
+        rl[i] = l;
+        split16(im, h, l);
+        ih[i] = h;
+        il[i] = l;
     }
 };
 
@@ -122,6 +170,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
     constexpr int NACC = GLS ? 6 : 4;
     __shared__ MfmaLds<NB, GLS> S;
     const int tid = threadIdx.x;
+    const float one = opaque_one();
     const int nw = blockDim.x / kWave;  // waves in the workgroup (1 to 8)
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -188,12 +237,13 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
                 p -= rint(p);
                 const float ph = (float)p;
                 const float c = cos_rev(ph), s = sin_rev(ph);
-                const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
+                float c2, s2;
+                double_angle(c, s, kTrigScale, c2, s2);
                 _Float16 h, l;
                 split16(c * kTrigScale, h, l); v[RR_H][i] = h; v[RR_L][i] = l;
                 split16(s * kTrigScale, h, l); v[RI_H][i] = h; v[RI_L][i] = l;
-                split16(c2 * kTrigScale, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
-                split16(s2 * kTrigScale, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
+                split16_sum(c2, one, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
+                split16(s2, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
             }
 #pragma unroll
             for (int q = 0; q < R_KINDS; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
@@ -211,16 +261,20 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
                 const float ph = (float)p;
                 const float c = cos_rev(ph), s = sin_rev(ph);
                 const float xv = S.x[js + i];
-                const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
                 L.set(i, xv * c, xv * s);
+                float c2, s2;
                 if (GLS) {
                     const float wv = S.w[js + i];
                     LW.set(i, wv * c, wv * s);
-                    L2.set(i, wv * c2, wv * s2);
+                    double_angle(c, s, wv, c2, s2);
                 } else {
-                    L2.set(i, c2 * kTrigScale, s2 * kTrigScale);
+                    double_angle(c, s, kTrigScale, c2, s2);
                 }
+                L2.set_sum(i, c2, s2, one);
             }
+            L.finish();
+            L2.finish();
+            if (GLS) LW.finish();
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 const int bcol = 32 * n + row;
@@ -326,6 +380,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
     __shared__ MfmaLds<2, false> S;
     __shared__ unsigned int s_item;
     const int tid = threadIdx.x;
+    const float one = opaque_one();
     const int nw = blockDim.x / kWave;
     const int lane = tid & (kWave - 1);
     const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -387,12 +442,13 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                     p -= rint(p);
                     const float ph = (float)p;
                     const float c = cos_rev(ph), s = sin_rev(ph);
-                    const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
+                    float c2, s2;
+                    double_angle(c, s, kTrigScale, c2, s2);
                     _Float16 h, l;
                     split16(c * kTrigScale, h, l); v[RR_H][i] = h; v[RR_L][i] = l;
                     split16(s * kTrigScale, h, l); v[RI_H][i] = h; v[RI_L][i] = l;
-                    split16(c2 * kTrigScale, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
-                    split16(s2 * kTrigScale, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
+                    split16_sum(c2, one, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
+                    split16(s2, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
                 }
 #pragma unroll
                 for (int q = 0; q < R_KINDS; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
@@ -409,10 +465,13 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                     const float ph = (float)p;
                     const float c = cos_rev(ph), s = sin_rev(ph);
                     const float xv = S.x[js + i];
-                    const float c2 = (c - s) * (c + s), s2 = 2.0f * c * s;
                     L.set(i, xv * c, xv * s);
-                    L2.set(i, c2 * kTrigScale, s2 * kTrigScale);
+                    float c2, s2;
+                    double_angle(c, s, kTrigScale, c2, s2);
+                    L2.set_sum(i, c2, s2, one);
                 }
+                L.finish();
+                L2.finish();
 #pragma unroll
                 for (int n = 0; n < 2; ++n) {
                     const int bcol = 32 * n + row;
@@ -616,6 +675,7 @@ struct MhStep {
                 COp LW;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) LW.set(i, wv[i] * er[i], wv[i] * ei[i]);
+                LW.finish();
                 LSP_CMAC(LW, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
             }
             if constexpr (P::value(M)) {
@@ -623,6 +683,7 @@ struct MhStep {
                 COp LX;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) LX.set(i, xv[i] * er[i], xv[i] * ei[i]);
+                LX.finish();
                 LSP_CMAC(LX, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
             }
         }
