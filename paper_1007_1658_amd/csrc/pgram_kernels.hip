@@ -38,36 +38,60 @@ __global__ void __launch_bounds__(256) prep_moments_kernel(const double *__restr
     if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
 
-__global__ void __launch_bounds__(256) prep_finalize_kernel(const Moments *__restrict__ part, int n_part,
-                                                            int phase, CurveStats *__restrict__ st)
+// all partial moments merged in a fixed order (every caller gets the same bits)
+__device__ __forceinline__ Moments merge_parts(const Moments *__restrict__ part, int n_part)
 {
     Moments m = moments_empty();
     for (int i = threadIdx.x; i < n_part; i += 256) m = moments_merge(m, part[i]);
-    m = block_merge_256(m);
-    if (threadIdx.x == 0) {
-        CurveStats s;
-        s.mean = m.mean;
-        s.var = m.m2 / m.n;
-        s.zero_var = (m.m2 > 0.0) ? 0 : 1;
-        s.inv_var = s.zero_var ? 0.0 : 1.0 / s.var;
-        s.t_min = m.tmin;
-        s.t_max = m.tmax;
-        s.wsum = m.n;
-        s.t_ref = (phase == PH_NAIVE) ? 0.0 : 0.5 * (m.tmin + m.tmax);
-        s.pad_ = 0;
-        *st = s;
-    }
+    return block_merge_256(m);
 }
+
+// the curve's scalars from its merged moments
+__device__ __forceinline__ CurveStats stats_of(const Moments &m, int phase)
+{
+    CurveStats s;
+    s.mean = m.mean;
+    s.var = m.m2 / m.n;
+    s.zero_var = (m.m2 > 0.0) ? 0 : 1;
+    s.inv_var = s.zero_var ? 0.0 : 1.0 / s.var;
+    s.t_min = m.tmin;
+    s.t_max = m.tmax;
+    s.wsum = m.n;
+    s.t_ref = (phase == PH_NAIVE) ? 0.0 : 0.5 * (m.tmin + m.tmax);
+    s.pad_ = 0;
+    return s;
+}
+
+__global__ void __launch_bounds__(256) prep_finalize_kernel(const Moments *__restrict__ part, int n_part,
+                                                            int phase, CurveStats *__restrict__ st)
+{
+    const Moments m = merge_parts(part, n_part);
+    if (threadIdx.x == 0) *st = stats_of(m, phase);
+}
+
+// Records, with the scalars merged by every block itself (one launch fewer than
+// a separate finalize step); block 0 also stores them for the later kernels.
+// The grid is bounded (kRecordBlocks) and strides over the samples, so the
+// merge is repeated at most that many times.
+constexpr int kRecordBlocks = 1024;
 
 __global__ void __launch_bounds__(256) prep_records_kernel(const double *__restrict__ t,
                                                            const float *__restrict__ x, int64_t Nt,
-                                                           const CurveStats *__restrict__ st,
-                                                           double step_df, int phase, Records rec)
+                                                           const Moments *__restrict__ part, int n_part,
+                                                           CurveStats *__restrict__ st, double step_df,
+                                                           int phase, Records rec)
 {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= Nt) return;
-    CurveStats s = *st;
-    write_record(rec, j, t[j], x[j], s, step_df, phase);
+    const CurveStats s = stats_of(merge_parts(part, n_part), phase);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st = s;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < Nt; j += stride)
+        write_record(rec, j, t[j], x[j], s, step_df, phase);
+}
+
+static unsigned record_blocks(int64_t Nt)
+{
+    const int64_t nb = (Nt + 255) / 256;
+    return (unsigned)(nb < kRecordBlocks ? (nb > 0 ? nb : 1) : kRecordBlocks);
 }
 
 hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_df, int phase,
@@ -75,11 +99,8 @@ hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_
                        hipStream_t s)
 {
     hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
-    hipLaunchKernelGGL(prep_finalize_kernel, dim3(1), dim3(256), 0, s, (const Moments *)moments,
-                       n_moment_blocks, phase, stats);
-    int64_t nb = (Nt + 255) / 256;
-    hipLaunchKernelGGL(prep_records_kernel, dim3((unsigned)nb), dim3(256), 0, s, t, x, Nt,
-                       (const CurveStats *)stats, step_df, phase, rec);
+    hipLaunchKernelGGL(prep_records_kernel, dim3(record_blocks(Nt)), dim3(256), 0, s, t, x, Nt,
+                       (const Moments *)moments, n_moment_blocks, stats, step_df, phase, rec);
     return hipGetLastError();
 }
 
@@ -109,31 +130,33 @@ __global__ void __launch_bounds__(256) prep_moments_w_kernel(const double *__res
     if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
 
+// weighted records; the scalars merged per block as in prep_records_kernel
 __global__ void __launch_bounds__(256) prep_records_w_kernel(const double *__restrict__ t,
                                                              const float *__restrict__ y,
                                                              const float *__restrict__ w, int64_t Nt,
-                                                             const CurveStats *__restrict__ st, Records rec)
+                                                             const Moments *__restrict__ part, int n_part,
+                                                             CurveStats *__restrict__ st, Records rec)
 {
-    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= Nt) return;
-    const CurveStats s = *st;
-    const double tp = t[j] - s.t_ref;
-    const float th = (float)tp;
-    rec.th[j] = th;
-    rec.tl[j] = (float)(tp - (double)th);
-    const double wn = (s.wsum > 0.0) ? (w ? (double)w[j] : 1.0) / s.wsum : 0.0;
-    rec.xv[j] = (float)(wn * ((double)y[j] - s.mean));
-    rec.wv[j] = (float)wn;
+    const CurveStats s = stats_of(merge_parts(part, n_part), (int)PH_SPLIT);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *st = s;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < Nt; j += stride) {
+        const double tp = t[j] - s.t_ref;
+        const float th = (float)tp;
+        rec.th[j] = th;
+        rec.tl[j] = (float)(tp - (double)th);
+        const double wn = (s.wsum > 0.0) ? (w ? (double)w[j] : 1.0) / s.wsum : 0.0;
+        rec.xv[j] = (float)(wn * ((double)y[j] - s.mean));
+        rec.wv[j] = (float)wn;
+    }
 }
 
 hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
                                 int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s)
 {
     hipLaunchKernelGGL(prep_moments_w_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, y, w, Nt, moments);
-    hipLaunchKernelGGL(prep_finalize_kernel, dim3(1), dim3(256), 0, s, (const Moments *)moments,
-                       n_moment_blocks, (int)PH_SPLIT, stats);
-    hipLaunchKernelGGL(prep_records_w_kernel, dim3((unsigned)((Nt + 255) / 256)), dim3(256), 0, s, t, y, w, Nt,
-                       (const CurveStats *)stats, rec);
+    hipLaunchKernelGGL(prep_records_w_kernel, dim3(record_blocks(Nt)), dim3(256), 0, s, t, y, w, Nt,
+                       (const Moments *)moments, n_moment_blocks, stats, rec);
     return hipGetLastError();
 }
 
