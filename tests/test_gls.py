@@ -98,3 +98,22 @@ def test_gls_epoch_offset_times_sampled():
     print(f"gls c2 sampled rel err {err:.3e}", flush=True)
     assert err <= REL_TOL
     assert abs(int(np.argmax(Pg)) - k0) <= 1
+
+
+def test_gls_long_series_sampled():
+    """2^20 weighted samples: the records kernel (bounded grid, each block
+    merging the moments itself) strides over them; oracle on sampled bins."""
+    Nt, Nf = 1 << 20, 4096
+    t, y, w = _case(Nt, 3, True)
+    df = 1.0 / (4 * (t[-1] - t[0]))
+    print(f"gls long Nt={Nt} Nf={Nf}", flush=True)
+    td, yd, wd = _dev(t, y, w)
+    Pg = lsp.lsp_gls(td, yd, df, df, Nf, w=wd).cpu().numpy()
+    g = np.random.default_rng(11)
+    kpk = int(np.argmax(Pg))
+    k = np.unique(np.concatenate([g.integers(0, Nf, 48), np.arange(max(0, kpk - 3), min(Nf, kpk + 4))]))
+    P = oracle.gls(t, y.astype(np.float64), df, df, k=k, w=w.astype(np.float64))
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
+    print(f"gls long sampled rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert abs((kpk + 1) * df - 1.3) <= 1.5 * df
