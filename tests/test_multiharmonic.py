@@ -91,6 +91,28 @@ def test_multiharmonic_full_size_sampled(K):
     assert err <= REL_TOL
 
 
+def test_multiharmonic_long_series_sampled():
+    """K = 2 on 2^20 weighted samples: the records kernel (bounded grid, each
+    block merging the moments itself) strides over them; oracle on sampled
+    well-conditioned bins."""
+    Nt, Nf, K = 1 << 20, 2048, 2
+    t, y, w = _case(Nt, 3, True)
+    df = 1.0 / (4 * (t[-1] - t[0]))
+    print(f"mh long Nt={Nt} Nf={Nf} K={K}", flush=True)
+    td, yd, wd = _dev(t, y, w)
+    Pg = lsp.lsp_multiharmonic(td, yd, K, df, df, Nf, w=wd).cpu().numpy()
+    g = np.random.default_rng(12)
+    kpk = int(np.argmax(Pg))
+    k = np.unique(np.concatenate([g.integers(0, Nf, 32), np.arange(max(0, kpk - 3), min(Nf, kpk + 4))]))
+    P = oracle.multiharmonic(t, y.astype(np.float64), K, df, df, k=k, w=w.astype(np.float64))
+    good = _well_conditioned(t, w, df + k * df, K=K)
+    assert good.mean() >= 0.9
+    err = float(np.max(np.abs(Pg[k][good] - P[good])) / P.max())
+    print(f"mh long sampled rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert abs((kpk + 1) * df - 0.9) <= 1.5 * df
+
+
 def test_one_harmonic_is_lsp_gls_and_bad_K_raises():
     t, y, w = _case(900, 2, True)
     df = 1.0 / (4 * (t[-1] - t[0]))
