@@ -452,6 +452,31 @@ __device__ __forceinline__ float pn_from_sums(double XC, double XS, double CC, d
     return (float)(P * inv_var);
 }
 
+// v[q] += part[(s NV + q) Nf + k] over the chunks s in ascending order (the
+// split merge); U chunks' loads are issued together before they are added, so
+// that U NV loads per lane are in flight and the sum is the same as one chunk at
+// a time
+template <int NV, int U>
+__device__ __forceinline__ void sum_chunks(const float *__restrict__ part, int splits, int64_t Nf, int64_t k,
+                                           double (&v)[NV])
+{
+    int s = 0;
+    for (; s + U <= splits; s += U) {
+        float f[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) f[u][q] = part[((int64_t)(s + u) * NV + q) * Nf + k];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] += (double)f[u][q];
+    }
+    for (; s < splits; ++s)
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] += (double)part[((int64_t)s * NV + q) * Nf + k];
+}
+
 // number of neutral samples that pad [0, Nt) to whole tiles
 __host__ __device__ __forceinline__ int64_t pad_count(int64_t Nt)
 {

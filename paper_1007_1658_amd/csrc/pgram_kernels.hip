@@ -200,9 +200,7 @@ __global__ void __launch_bounds__(256) pgram_reduce_kernel(const float *__restri
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= Nf) return;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < splits; ++s)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] += (double)part[((int64_t)s * 4 + q) * Nf + k];
+    sum_chunks<4, 8>(part, splits, Nf, k, v);
     v[2] -= (double)pad_count(Nt);  // chunks are whole tiles except the last
     Pn[k] = pn_from_sums(v[0], v[1], v[2], v[3], (double)Nt, st->inv_var);
 }

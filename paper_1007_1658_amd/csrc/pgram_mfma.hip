@@ -544,9 +544,7 @@ __global__ void __launch_bounds__(256) gls_reduce_kernel(const float *__restrict
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= Nf) return;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int s = 0; s < splits; ++s)
-#pragma unroll
-        for (int q = 0; q < 6; ++q) v[q] += (double)part[((int64_t)s * 6 + q) * Nf + k];
+    sum_chunks<6, 4>(part, splits, Nf, k, v);
     const double C = v[0], Sn = v[1], YC = v[2], YS = v[3];
     const double CCh = 0.5 + v[4], CSh = v[5];
     const double CC = CCh - C * C, SS = (1.0 - CCh) - Sn * Sn, CS = CSh - C * Sn;
@@ -830,9 +828,7 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
     double v[2 * NS];
 #pragma unroll
     for (int q = 0; q < 2 * NS; ++q) v[q] = 0.0;
-    for (int s = 0; s < splits; ++s)
-#pragma unroll
-        for (int q = 0; q < 2 * NS; ++q) v[q] += (double)part[((int64_t)s * 2 * NS + q) * Nf + k];
+    sum_chunks<2 * NS, (2 * NS >= 24 ? 1 : 2)>(part, splits, Nf, k, v);
     double C[M2 + 1], Sn[M2 + 1];
     C[0] = 1.0;
     Sn[0] = 0.0;
