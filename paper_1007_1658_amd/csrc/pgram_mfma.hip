@@ -413,7 +413,18 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
         (void)frexpf(mx, &ex);
         const float xscale = ldexpf(1.0f, 14 - ex);
 
-        const int64_t a0 = ((int64_t)item.fblock * nw + wave) * 32;
+        // A curve's last item may hold fewer than nw row tiles with frequencies
+        // below Nf.  With at most two (one), the waves group in twos (fours) on
+        // them: the waves of a group take one row tile and split each block's
+        // four K-steps between them (all waves still share the block's R
+        // operands), and their sums are added through LDS at the end.
+        const int64_t k_first = (int64_t)item.fblock * nw * 32 * 64;
+        const int64_t n_act = (cv.Nf - k_first + 2047) / 2048;
+        const int grp = (nw != 4) ? 1 : (n_act <= 1 ? 4 : (n_act <= 2 ? 2 : 1));  // waves per row tile
+        const int tiles = nw / grp;
+        const int tile = wave % tiles;
+        const int kg = wave / tiles;   // the wave's share of the K-steps within its group
+        const int64_t a0 = ((int64_t)item.fblock * nw + tile) * 32;
         const double Fa = cv.f_min + (double)((a0 + row) * 64) * cv.df;
         floatx16 acc[2][4];
 #pragma unroll
@@ -456,6 +467,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
             __syncthreads();
 #pragma unroll
             for (int ks = 0; ks < kMB / 16; ++ks) {
+                if (ks / (4 / grp) != kg) continue;  // another wave of the group takes it
                 const int js = 16 * ks + 8 * half;
                 COp L, L2;
 #pragma unroll
@@ -489,6 +501,33 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
             }
         }
 
+        // group sums by a fixed tree through the R staging area: in each round
+        // the upper half of the group (two waves in all, 64 KB of the 72 KB)
+        // stores its sums and the lower half adds them
+        float *ps = reinterpret_cast<float *>(&S.R[0][0][0]);
+        for (int h = grp / 2; h >= 1; h /= 2) {
+            __syncthreads();  // the R operands (first round) or the last round's sums are read
+            if (kg >= h && kg < 2 * h) {
+                const int slot = (kg - h) * tiles + tile;
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) ps[(slot * 128 + n * 64 + q * 16 + r) * kWave + lane] = acc[n][q][r];
+            }
+            __syncthreads();
+            if (kg < h) {
+                const int slot = kg * tiles + tile;
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int r = 0; r < 16; ++r) acc[n][q][r] += ps[(slot * 128 + n * 64 + q * 16 + r) * kWave + lane];
+            }
+        }
+        if (kg > 0) continue;  // the group's first wave evaluates the tile
         // whole-curve sums; the ragged end was padded with samples at t' = 0,
         // x = 0, each adding 1 to Re of the double-angle sum
         const double ux = ldexp(1.0, ex - 28);
