@@ -123,3 +123,35 @@ def test_batched_stratified_c3_subset():
         i = int(np.nonzero(kk == kbest[c])[0][0])
         assert abs(pmax[c] - P[i]) <= REL_TOL * P.max()
         assert P.max() - P[i] <= REL_TOL * P.max() + 1e-12   # no sampled bin beats the reported peak
+
+
+def test_batched_last_item_tile_counts():
+    """Curves whose last 8192-frequency item holds 1, 2, 3 or 4 row tiles of
+    2048 frequencies below Nf (the matrix-core form shares a sparse last item
+    between groups of waves that split its K-steps); oracle on every bin."""
+    g = np.random.default_rng(77)
+    tails = [100, 2048, 2100, 4096, 4200, 6144, 6200, 8192]
+    ts, xs, nts = [], [], []
+    for c, tail in enumerate(tails):
+        Nt = 300 + 45 * c
+        t = np.sort(g.uniform(0.0, 50.0, Nt))
+        x = (np.sin(2 * np.pi * (3.0 + c) * t) + g.normal(0, 1.0, Nt)).astype(np.float32)
+        ts.append(t); xs.append(x); nts.append(Nt)
+    off = np.concatenate([[0], np.cumsum(nts)]).astype(np.int64)
+    df = np.full(len(tails), 1.0 / 200.0)
+    Nf = np.array([8192 + tl for tl in tails], dtype=np.int64)
+    b = synth.Batch(np.concatenate(ts), np.concatenate(xs), off, df.copy(), df, Nf, "tails")
+    print(f"batched last-item tiles Nf={Nf.tolist()}", flush=True)
+    t, x = _dev(b)
+    out = lsp.lsp_periodogram_batched(t, x, b.off, b.f_min, b.df, b.Nf, want_pn=True)
+    Pn = out["Pn"].cpu().numpy()
+    kbest = out["kbest"].cpu().numpy()
+    pn_off = np.concatenate([[0], np.cumsum(b.Nf)])
+    for c in range(b.n):
+        cv = b.curve(c)
+        P = oracle.periodogram(cv.t, cv.x, cv.f_min, cv.df, Nf=cv.Nf)
+        Pg = Pn[pn_off[c]:pn_off[c + 1]]
+        assert rel_err(Pg, P) <= REL_TOL, c
+        assert kbest[c] == int(np.argmax(Pg))
+        ko = int(np.argmax(P))
+        assert kbest[c] == ko or P[ko] - P[kbest[c]] <= REL_TOL * P[ko]
