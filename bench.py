@@ -23,13 +23,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Nt·Nf terms/s (split-FP32 vs plain) at max|ΔPn|≤1e-4; % FP32 VALU peak"
-FLOP_PER_TERM = 13          # phase mul/round/sub 3, sin+cos 2, four FMAs 8
-PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz, packed issue)
-# matrix-core form: per term, two complex products (XC + i XS and the
-# double-angle sum), each 4 real products in three FP16 passes: 24 multiply-adds
-MFMA_FLOP_PER_TERM = 48
+# The method's work per term, fixed before optimizing and the same for every
+# kernel form: phase multiply, round and subtract (3), sin and cos (2), four
+# multiply-adds into XC, XS, CC, CS (8).  Every roofline fraction below divides
+# this work by the peak of the arithmetic the kernel actually runs on.
+FLOP_PER_TERM = 13
+PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz)
 PEAK_FP16_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
-PEAK_CLOCK_GHZ = 2.4        # the clock both published peaks assume
+# what the matrix-core form issues per term (a secondary figure, not the
+# method's work): two complex products (XC + i XS and the double-angle sum),
+# each four real products in three FP16 hi/lo passes, 24 multiply-adds
+MFMA_ISSUED_FLOP_PER_TERM = 48
 REL_TOL = 1e-4
 
 WORKLOADS = {
@@ -49,8 +53,17 @@ WORKLOADS = {
     "fast": ("extirpolation + FFT approximation (Press & Rybicki), macc 4, on c1: Nt=65536, Nf=131072; "
              "Nt*Nf terms/s of the direct sums it replaces"),
 }
-GLS_FLOP_PER_TERM = 72      # three complex products in three FP16 passes: 36 multiply-adds
-MH_FLOP_PER_HARMONIC = 72   # per term and harmonic: three complex products in three FP16 passes
+# The weighted periodograms' work per term, by the same rule as FLOP_PER_TERM.
+# Generalized: phase 3, sin and cos 2, w cos and w sin 4, (w y) cos and (w y) sin 4,
+# w c then (w c) c and (w c) s 5: 18.  K harmonics: phase 3, sin and cos 2,
+# 2K - 1 complex products by e^{i w t} (6 each), 2K weighted harmonic sums (4 each),
+# K value sums (4 each): 24 K - 1.
+GLS_FLOP_PER_TERM = 18
+def MH_FLOP_PER_TERM(K):
+    return 24 * K - 1
+# what the matrix pipe issues per term: three complex products in three FP16
+# passes (36 multiply-adds) per harmonic
+ISSUED_FLOP_PER_HARMONIC = 72
 
 
 def make_curve(name):
@@ -88,13 +101,6 @@ def traffic_from_profiles(kernel_name, workload):
     return float(e["bytes_per_launch"]) if e and "bytes_per_launch" in e else None
 
 
-def clock_from_profiles(kernel_name, workload):
-    """Shader clock (GHz) during the kernel: GRBM_GUI_ACTIVE per XCD over the
-    kernel's average duration in the same profile, or None."""
-    e = profile_entry(kernel_name, workload)
-    return float(e["clock_ghz"]) if e and e.get("clock_ghz") else None
-
-
 def warm(fn, warmup, min_seconds=0.3):
     """W untimed steps, continued until the GPU has been busy min_seconds (clocks settle)."""
     import torch
@@ -108,16 +114,36 @@ def warm(fn, warmup, min_seconds=0.3):
     torch.cuda.synchronize()
 
 
-def time_steps(fn, steps, warmup, on_start=None):
+def time_steps(fn, steps, warmup, on_start=None, per_step=None):
+    """Seconds per step over exactly `steps` steps after `warmup` untimed ones.
+    per_step (a list) receives each step's own duration in ms, from events
+    recorded between the steps on the stream they run on (no host sync in
+    between, so they measure the same back-to-back run)."""
     import torch
     warm(fn, warmup)
     if on_start:
         on_start()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step is not None else None
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if ev:
+            ev[i].record()
+        fn()
+    if ev:
+        ev[steps].record()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    if ev:
+        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return sec
+
+
+def step_stats(ms):
+    a = np.asarray(ms, dtype=np.float64)
+    return {"n": int(a.size), "median_ms": float(np.median(a)), "mean_ms": float(a.mean()),
+            "std_ms": float(a.std(ddof=1)) if a.size > 1 else 0.0,
+            "min_ms": float(a.min()), "max_ms": float(a.max())}
 
 
 def sampled_error(curve, Pg, n=256, seed=0):
@@ -157,7 +183,30 @@ def cpu_baseline(curve, target_s):
         "kind": "oracle",
         "sample": (f"FP64 two-pass oracle over all Nt={curve.Nt} samples at {nb} of the {curve.Nf} "
                    f"frequencies (random subset), {el:.1f} s on {cores} threads"),
+        "one_thread": one_thread_baseline(curve),
     }
+
+
+def one_thread_baseline(curve):
+    """The oracle on one host thread: c0 in full (5 runs, mean and sigma, as the
+    paper averages five runs) and 128 random frequencies of this workload."""
+    import oracle
+    from paper_1007_1658_amd import synth
+    c0 = synth.c0()
+    runs = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.periodogram(c0.t, c0.x, c0.f_min, c0.df, Nf=c0.Nf, threads=1)
+        runs.append(time.perf_counter() - t0)
+    r = np.asarray(runs)
+    k = np.sort(np.random.default_rng(8).choice(curve.Nf, size=min(128, curve.Nf), replace=False))
+    t0 = time.perf_counter()
+    oracle.periodogram(curve.t, curve.x, curve.f_min, curve.df, k=k, threads=1)
+    el = time.perf_counter() - t0
+    return {"c0_terms_per_s": c0.Nt * c0.Nf / r.mean(), "c0_seconds_mean": float(r.mean()),
+            "c0_seconds_std": float(r.std(ddof=1)),
+            "subset_terms_per_s": curve.Nt * k.size / el,
+            "subset": f"{k.size} random frequencies x all {curve.Nt} samples, {el:.2f} s"}
 
 
 def calib_copy(mib):
@@ -237,12 +286,15 @@ def run_batched(args):
         "latency_ms": {"run_p50": float(np.percentile(lat_run, 50)), "run_p99": float(np.percentile(lat_run, 99)),
                        "done_p50": float(np.percentile(lat_done, 50)), "done_p99": float(np.percentile(lat_done, 99))},
         "peak_rel_err_sampled": worst,
-        "roofline": ({"bound": "mfma", "achieved": MFMA_FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP16_TFLOPS,
-                      "unit": "TFLOP/s", "frac": MFMA_FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP16_TFLOPS,
-                      "traffic": None, "kernel": "batch_mfma_kernel (whole graph)"} if mfma else
+        "roofline": ({"bound": "mfma", "achieved": FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP16_TFLOPS,
+                      "unit": "TFLOP/s", "frac": FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP16_TFLOPS,
+                      "flop_per_term": FLOP_PER_TERM, "traffic": None, "kernel": "batch_mfma_kernel (whole graph)",
+                      "mfma_issued_frac": MFMA_ISSUED_FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP16_TFLOPS}
+                     if mfma else
                      {"bound": "alu", "achieved": FLOP_PER_TERM * terms / sec / 1e12, "peak": PEAK_FP32_TFLOPS,
                       "unit": "TFLOP/s", "frac": FLOP_PER_TERM * terms / sec / 1e12 / PEAK_FP32_TFLOPS,
-                      "traffic": None, "kernel": "batch_pgram_kernel (whole graph)"}),
+                      "flop_per_term": FLOP_PER_TERM, "traffic": None,
+                      "kernel": "batch_pgram_kernel (whole graph)"}),
     }
     print(json.dumps(line), flush=True)
 
@@ -275,9 +327,9 @@ def run_gls(args):
     pg = p.cpu().numpy()
     g = np.random.default_rng(0)
     kpk = int(np.argmax(pg))
-    k = np.unique(np.concatenate([g.integers(0, c.Nf, 256), np.arange(max(0, kpk - 4), min(c.Nf, kpk + 5))]))
+    k = np.unique(np.concatenate([g.integers(0, c.Nf, 256), np.arange(max(0, kpk - 4), min(c.Nf, kpk + 5)),
+                                  np.arange(0, 8)]))
     if mh:
-        k = k[k >= 2 * K]   # a few cycles per baseline: the normal equations are well conditioned
         P = oracle.multiharmonic(c.t, c.x.astype(np.float64), K, c.f_min, c.df, k=k, w=w.astype(np.float64))
     else:
         P = oracle.gls(c.t, c.x.astype(np.float64), c.f_min, c.df, k=k, w=w.astype(np.float64))
@@ -287,8 +339,8 @@ def run_gls(args):
     lsp.lsp_profile_enable(False)
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     terms = c.Nt * c.Nf
-    flop = MH_FLOP_PER_HARMONIC * K if mh else GLS_FLOP_PER_TERM
-    clock = clock_from_profiles(k_name, args.config)
+    flop = MH_FLOP_PER_TERM(K) if mh else GLS_FLOP_PER_TERM
+    issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1)
     achieved = flop * terms / k_avg_s / 1e12
     line = {
         "metric": (f"Nt·Nf terms/s of the multi-harmonic (K={K}) periodogram at max|Δp|≤1e-4" if mh else
@@ -300,9 +352,8 @@ def run_gls(args):
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP16_TFLOPS, "traffic": traffic_from_profiles(k_name, args.config),
                      "kernel": k_name, "kernel_avg_ms": k_avg_s * 1e3, "flop_per_term": flop,
-                     "clock_ghz_profiled": clock,
-                     "frac_at_profiled_clock": None if clock is None else
-                     achieved / (PEAK_FP16_TFLOPS * clock / PEAK_CLOCK_GHZ)},
+                     "mfma_issued": {"flop_per_term": issued,
+                                     "frac": issued * terms / k_avg_s / 1e12 / PEAK_FP16_TFLOPS}},
     }
     print(json.dumps(line), flush=True)
 
@@ -418,7 +469,9 @@ def main():
     err_split = sampled_error(curve, Pn.cpu().numpy())
 
     # the profiling hook brackets the main kernel of the timed steps only
-    sec = time_steps(run_split, args.steps, args.warmup, on_start=lambda: lsp.lsp_profile_enable(True))
+    steps_ms = []
+    sec = time_steps(run_split, args.steps, args.warmup, on_start=lambda: lsp.lsp_profile_enable(True),
+                     per_step=steps_ms)
     k_ms, k_n, k_name = lsp.lsp_profile_read()
     lsp.lsp_profile_enable(False)
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
@@ -451,20 +504,45 @@ def main():
         run_valu()
         torch.cuda.synchronize()
         err_v = sampled_error(curve, Pv.cpu().numpy())
-        sec_v = time_steps(run_valu, max(5, args.steps // 2), 2, on_start=lambda: lsp.lsp_profile_enable(True))
+        v_ms = []
+        sec_v = time_steps(run_valu, max(20, args.steps // 2), 2, on_start=lambda: lsp.lsp_profile_enable(True),
+                           per_step=v_ms)
         kv_ms, kv_n, kv_name = lsp.lsp_profile_read()
         lsp.lsp_profile_enable(False)
         kv_s = kv_ms / 1e3 / max(kv_n, 1)
-        valu = {"value": terms / sec_v, "ms_per_step": sec_v * 1e3, "kernel": kv_name, "kernel_avg_ms": kv_s * 1e3,
-                "frac_fp32_valu_peak": FLOP_PER_TERM * terms / kv_s / 1e12 / PEAK_FP32_TFLOPS,
+        ach_v = FLOP_PER_TERM * terms / kv_s / 1e12
+        valu = {"value": terms / sec_v, "ms_per_step": sec_v * 1e3, "step_stats": step_stats(v_ms),
+                "kernel": kv_name, "kernel_avg_ms": kv_s * 1e3,
+                "frac_fp32_valu_peak": ach_v / PEAK_FP32_TFLOPS,
+                "frac_fp32_valu_peak_whole_call": FLOP_PER_TERM * terms / sec_v / 1e12 / PEAK_FP32_TFLOPS,
+                "roofline": {"bound": "alu", "achieved": ach_v, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                             "frac": ach_v / PEAK_FP32_TFLOPS, "flop_per_term": FLOP_PER_TERM,
+                             "traffic": traffic_from_profiles(kv_name, args.config)},
                 "max_rel_err": err_v, "meets_1e-4": bool(err_v <= REL_TOL)}
 
     mfma = "mfma" in k_name
-    flop = MFMA_FLOP_PER_TERM if mfma else FLOP_PER_TERM
     peak = PEAK_FP16_TFLOPS if mfma else PEAK_FP32_TFLOPS
-    achieved = flop * terms / k_avg_s / 1e12
+    # the method's 13 FLOP per term over the kernel's time, against the peak of
+    # the arithmetic the kernel runs on (FP16 matrix cores or FP32 vector)
+    achieved = FLOP_PER_TERM * terms / k_avg_s / 1e12
     traffic = traffic_from_profiles(k_name, args.config)
-    clock = clock_from_profiles(k_name, args.config)
+    roof = {
+        "bound": "mfma" if mfma else "alu",
+        "achieved": achieved,
+        "peak": peak,
+        "unit": "TFLOP/s",
+        "frac": achieved / peak,
+        "traffic": traffic,
+        "kernel": k_name,
+        "kernel_avg_ms": k_avg_s * 1e3,
+        "flop_per_term": FLOP_PER_TERM,
+    }
+    if mfma:
+        # what the matrix pipe issues: 48 FLOP per term (two complex products,
+        # four real products each, three FP16 hi/lo passes)
+        issued = MFMA_ISSUED_FLOP_PER_TERM * terms / k_avg_s / 1e12
+        roof["mfma_issued"] = {"flop_per_term": MFMA_ISSUED_FLOP_PER_TERM, "achieved": issued,
+                               "frac": issued / PEAK_FP16_TFLOPS}
     line = {
         "metric": METRIC,
         "value": value,
@@ -473,6 +551,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec * 1e3,
+        "step_stats": step_stats(steps_ms),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -485,22 +564,7 @@ def main():
         "meets_1e-4": bool(err_split <= REL_TOL),
         "plain": plain,
         "valu_form": valu,
-        "roofline": {
-            "bound": "mfma" if mfma else "alu",
-            "achieved": achieved,
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": achieved / peak,
-            "traffic": traffic,
-            "kernel": k_name,
-            "kernel_avg_ms": k_avg_s * 1e3,
-            "flop_per_term": flop,
-            # the same kernel time priced as the FP32-vector form's 13 FLOP per term
-            "fp32_valu_equiv_frac": FLOP_PER_TERM * terms / k_avg_s / 1e12 / PEAK_FP32_TFLOPS,
-            # the published peak assumes 2.4 GHz; the fraction at the clock the profile saw
-            "clock_ghz_profiled": clock,
-            "frac_at_profiled_clock": None if clock is None else achieved / (peak * clock / PEAK_CLOCK_GHZ),
-        },
+        "roofline": roof,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
     }
     if args.config == "paper":

@@ -222,6 +222,14 @@ lsp_status lsp_multiharmonic(const double *t, const float *y, const float *w, in
    t_ns      device uint64 [2n] or NULL: device timestamps (ns, relative to
              the start of the launch) at which curve c's first work item
              started and its last work item finished.
+   The call may be captured by the caller (torch.cuda.graph or
+   hipStreamBeginCapture) once an uncaptured call with the same shape has
+   prepared the stream's workspace; the captured graph keeps reading that
+   workspace's plan tables, so a later uncaptured call with another shape on
+   the same stream moves to a fresh workspace (the captured one is kept until
+   the process ends).  A captured graph and uncaptured calls of the same shape
+   share one workspace: replays and calls that overlap in time (on different
+   streams) race.
    Errors: LSP_ERR_INVALID_ARG; LSP_ERR_CAPTURE when the stream is being
    captured by the caller and this shape has not been prepared by an
    earlier uncaptured call. */
@@ -267,7 +275,9 @@ lsp_status lsp_mc_maxpower(const double *t, const int64_t *off, int32_t n_pat,
    frequency index k in [round(Nf^(b/64)) - 1, round(Nf^((b+1)/64)) - 1),
    outer edges 0 and Nf (at least one k each); feat[p*68 + 64..67]: log10 Nt, log10 T, gap fraction
    (the spacings longer than five mean spacings, summed, over T; times must be
-   sorted), log10 Nf.  feat: device FP32 [n_pat][68].  Asynchronous. */
+   sorted), log10 Nf.  feat: device FP32 [n_pat][68].  Asynchronous.
+   lsp_mc_maxpower and this call upload their work tables synchronously, so
+   neither can be captured: LSP_ERR_CAPTURE on a capturing stream. */
 lsp_status lsp_window_features(const double *t, const int64_t *off, int32_t n_pat,
                                const double *f_min, const double *df, const int64_t *Nf,
                                float *feat, void *stream);
@@ -403,6 +413,37 @@ lsp_status lsp_tune_cache_load(const char *path);
    lane-operations (kinds 4-7: FLOPs) per second; ms may be NULL. */
 lsp_status lsp_microbench(int32_t kind, int32_t waves_per_simd, int32_t iters,
                           void *stream, double *ops_per_s, double *ms);
+
+/* ---- probes of the kernels' building blocks ---------------------------------------
+
+   Each probe runs one building block of the periodogram kernels on
+   caller-given inputs, one element per lane, with the device code the kernels
+   themselves run, so that its error can be measured against an FP64 or 80-bit
+   reference.  All pointers are device memory; asynchronous on `stream`;
+   n = 0 does nothing.  LSP_ERR_INVALID_ARG for n < 0, NULL pointers (n > 0)
+   or non-finite scalars.
+
+   lsp_probe_sincos: s[i] = sin(2 pi r[i]), c[i] = cos(2 pi r[i]) by the
+   hardware sine and cosine, which take revolutions (Section 4.4 quotes the
+   maximum error of the G80 intrinsic the paper used).  r, s, c: FP32 [n].
+
+   lsp_probe_phase: the reduced phase phi[i] (revolutions, |phi| <= 1/2) of
+   frequency f[i] at time t[i] in phase mode `phase` (lsp_phase_mode), with
+   the time held as the records hold it: SPLIT and SPLIT32 reduce
+   f (t - t_ref) with t - t_ref in FP64 split into two FP32 halves; NAIVE
+   reduces fl32(f) fl32(t) in FP32 (t_ref unused).  t, f: FP64 [n]; phi: FP32 [n].
+
+   lsp_probe_recurrence: for each time t[i], the M values
+   (c, s)[i M + m] = (cos, sin)(2 pi (f0 + m step_df) (t[i] - t_ref)), m < M,
+   as the recurrence form (LSP_TRIG_RECUR) makes them: the hardware sine and
+   cosine of the SPLIT phase of f0, one rotation by the per-sample step angle
+   2 pi step_df t' (FP64, rounded to FP32), then the three-term recurrence.
+   The kernels use step_df = 64 df.  1 <= M <= 32; c, s: FP32 [n M]. */
+lsp_status lsp_probe_sincos(const float *r, int64_t n, float *s, float *c, void *stream);
+lsp_status lsp_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int32_t phase,
+                           float *phi, void *stream);
+lsp_status lsp_probe_recurrence(const double *t, int64_t n, double t_ref, double f0, double step_df,
+                                int32_t M, float *c, float *s, void *stream);
 
 /* ---- profiling hook ------------------------------------------------------------
 

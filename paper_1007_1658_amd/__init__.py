@@ -107,6 +107,9 @@ SIGNATURES = {
     "lsp_tune_cache_save": (_I32, [ctypes.c_char_p]),
     "lsp_tune_cache_load": (_I32, [ctypes.c_char_p]),
     "lsp_microbench": (_I32, [_I32, _I32, _I32, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "lsp_probe_sincos": (_I32, [_P, _I64, _P, _P, _P]),
+    "lsp_probe_phase": (_I32, [_P, _P, _I64, _D, _I32, _P, _P]),
+    "lsp_probe_recurrence": (_I32, [_P, _I64, _D, _D, _D, _I32, _P, _P, _P]),
     "lsp_profile_enable": (_I32, [_I32]),
     "lsp_profile_read": (_I32, [ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.c_char_p, _I32]),
     "lsp_grid_paper": (_I32, [_D, _D, _I64, _D, _D, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -463,6 +466,44 @@ def lsp_microbench(kind: int, waves_per_simd: int = 2, iters: int = 4096, stream
     _check(lib().lsp_microbench(int(kind), int(waves_per_simd), int(iters), _stream_ptr(stream),
                                 ctypes.byref(ops), ctypes.byref(ms)), "lsp_microbench")
     return ops.value, ms.value
+
+
+def lsp_probe_sincos(r, stream=None):
+    """(sin, cos)(2 pi r) by the hardware instructions the kernels use; r: device float32."""
+    torch = _torch()
+    _dev_tensor(r, torch.float32, "r")
+    s, c = torch.empty_like(r), torch.empty_like(r)
+    with torch.cuda.device(r.device):
+        _check(lib().lsp_probe_sincos(_ptr(r), r.numel(), _ptr(s), _ptr(c), _stream_ptr(stream)),
+               "lsp_probe_sincos")
+    return s, c
+
+
+def lsp_probe_phase(t, f, t_ref: float, phase="split", stream=None):
+    """Reduced phase of f[i] at t[i] in the given phase mode (device float64 t, f -> float32)."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(f, torch.float64, "f")
+    if f.numel() != t.numel():
+        raise ValueError("t and f differ in length")
+    phi = torch.empty(t.numel(), dtype=torch.float32, device=t.device)
+    with torch.cuda.device(t.device):
+        _check(lib().lsp_probe_phase(_ptr(t), _ptr(f), t.numel(), float(t_ref), PHASES[phase], _ptr(phi),
+                                     _stream_ptr(stream)), "lsp_probe_phase")
+    return phi
+
+
+def lsp_probe_recurrence(t, t_ref: float, f0: float, step_df: float, M: int, stream=None):
+    """(cos, sin)(2 pi (f0 + m step_df)(t - t_ref)), m < M, as the recurrence form makes them:
+    two device float32 tensors [n, M]."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    c = torch.empty((t.numel(), int(M)), dtype=torch.float32, device=t.device)
+    s = torch.empty_like(c)
+    with torch.cuda.device(t.device):
+        _check(lib().lsp_probe_recurrence(_ptr(t), t.numel(), float(t_ref), float(f0), float(step_df), int(M),
+                                          _ptr(c), _ptr(s), _stream_ptr(stream)), "lsp_probe_recurrence")
+    return c, s
 
 
 def lsp_profile_enable(on: bool = True):

@@ -104,15 +104,13 @@ __global__ void __launch_bounds__(256) batch_time_kernel(BatchArgs a)
     const double step_df = (double)kWave * g.df;
     for (int64_t j = threadIdx.x; j < g.Nt; j += 256) {
         const double tp = t[j] - t_ref;
-        const float th = (float)tp;
-        double q = step_df * tp;  // revolutions of the step angle
-        q -= rint(q);
-        double sq, cq;
-        sincospi(2.0 * q, &sq, &cq);
+        float th, tl, rc, rs;
+        split_time(tp, th, tl);
+        step_rotation(step_df, tp, rc, rs);
         a.th[g.toff + j] = th;
-        a.tl[g.toff + j] = (float)(tp - (double)th);
-        a.rc[g.toff + j] = (float)cq;
-        a.rs[g.toff + j] = (float)sq;
+        a.tl[g.toff + j] = tl;
+        a.rc[g.toff + j] = rc;
+        a.rs[g.toff + j] = rs;
     }
 }
 

@@ -54,6 +54,10 @@ struct PgramArgs {
     float *Pn;          // output, written by the reduce/epilogue kernel
     float *part;        // [splits][4][Nf] per-chunk sums (merged in FP64)
     int32_t splits;
+    // weighted periodograms: bins whose FP32-derived normal equations are
+    // ill-conditioned, listed by the merge for an FP64 recomputation
+    uint32_t *refine_list;   // [Nf]
+    uint32_t *refine_count;  // [1], zeroed by the weighted prep
 };
 
 // Batched work item: one wave computes 64*m frequencies of one curve.
@@ -133,11 +137,14 @@ __global__ void pgram_mfma_kernel(PgramArgs a);
 // the generalized periodogram (pgram_mfma.hip): weighted prep, matrix-core sums
 // (32 a-rows x 32 b per wave, six sums into part[splits][6][Nf]) and FP64 merge
 hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
-                                int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s);
+                                int n_moment_blocks, CurveStats *stats, Records rec, uint32_t *refine_count,
+                                hipStream_t s);
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // the multi-harmonic periodogram with K = 2 (pgram_mfma.hip): part[splits][12][Nf]
 hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;
+// FP64 recomputation of the bins the weighted merges listed (K = 1: generalized)
+hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s);
 
 // moments and CurveStats only (no records)
 hipError_t launch_moments(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
@@ -167,6 +174,14 @@ hipError_t launch_normals(uint64_t seed, uint64_t curve, int64_t n, float *out, 
 
 constexpr int kWindowBands = 64;    // log-spaced bands of the spectral-window features
 constexpr int kFeatures = kWindowBands + 4;
+
+// ---- probes of the kernels' building blocks (probe_kernels.hip) -------------------
+hipError_t launch_probe_sincos(const float *r, int64_t n, float *s, float *c, hipStream_t st);
+hipError_t launch_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int phase, float *phi,
+                              hipStream_t st);
+hipError_t launch_probe_recur(const double *t, int64_t n, double t_ref, double f0, double step_df, int M, float *c,
+                              float *s, hipStream_t st);
+int probe_recur_max();
 
 // records a message for lsp_last_error() on this host thread (lsp_host.cpp)
 void set_last_error(const char *msg);

@@ -119,6 +119,16 @@ bool stream_capturing(hipStream_t s)
     return st == hipStreamCaptureStatusActive;
 }
 
+// Sets a buffer that a captured graph refers to aside for the rest of the
+// process (it is never freed); the next ensure() allocates a fresh one.
+void retire(Buffer &b)
+{
+    if (b.ptr) b.retired.push_back(b.ptr);
+    b.ptr = nullptr;
+    b.size = 0;
+    b.captured = false;
+}
+
 // Grow-only buffer.  It never grows while the stream is captured, and a buffer
 // that a capture used is retired, not freed, when a later eager call outgrows
 // it: the captured graph keeps replaying into it.
@@ -334,6 +344,8 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     a.Pn = Pn;
     a.part = (float *)(base + L.part);
     a.splits = tile.splits;
+    a.refine_list = nullptr;
+    a.refine_count = nullptr;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (allow_profile && ctx().prof) {
@@ -587,7 +599,13 @@ static lsp_status batched_impl(const double *t, const float *x, const int64_t *o
             g_last_error = "batch shape not prepared before capture";
             return LSP_ERR_CAPTURE;
         }
+        // the caller's graph now reads this buffer's plan tables and writes its
+        // records: a later eager call with another plan must not touch it
+        sc.bws.captured = true;
     } else if (sc.plan_key != plan_key || sc.bws.size < L.total) {
+        // a plan that a captured graph replays is never overwritten or freed:
+        // the new plan goes to a fresh buffer and the old one is retired
+        if (sc.bws.captured) retire(sc.bws);
         st = ensure(sc.bws, L.total, s);
         if (st != LSP_OK) return st;
         st = upload_plan((char *)sc.bws.ptr, L, P, s);
@@ -655,6 +673,11 @@ static lsp_status mc_or_window(const double *t, const int64_t *off, int32_t n, c
     DeviceInfo *di = nullptr;
     lsp_status st = device_info(&dev, &di);
     if (st != LSP_OK) return st;
+    if (stream_capturing(s)) {
+        // every call uploads its plan tables synchronously
+        g_last_error = "Monte-Carlo and window calls cannot be captured";
+        return LSP_ERR_CAPTURE;
+    }
     const bool window = feat != nullptr;
     BatchPlan P;
     build_plan(off, n, f_min, df, Nf, window ? 1 : reps, P);
@@ -860,6 +883,10 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     const size_t o_part = o;
     const int slots = (K == 1) ? 6 : 6 * K;  // partial sums per frequency and chunk
     o = align_up(o + sizeof(float) * (size_t)slots * (size_t)Nf * (size_t)eff);
+    const size_t o_list = o;  // bins listed for the FP64 recomputation, and their count
+    o = align_up(o + sizeof(uint32_t) * (size_t)Nf);
+    const size_t o_count = o;
+    o = align_up(o + sizeof(uint32_t));
     StreamCtx &sc = stream_ctx(dev, s);
     st = ensure(sc.ws, o, s);
     if (st != LSP_OK) return st;
@@ -872,7 +899,8 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     rec.rc = nullptr;
     rec.rs = nullptr;
     CurveStats *stats = (CurveStats *)(base + o_stats);
-    hipError_t e = launch_prep_weighted(t, y, w, Nt, (Moments *)(base + o_mom), n_mom, stats, rec, s);
+    uint32_t *refine_count = (uint32_t *)(base + o_count);
+    hipError_t e = launch_prep_weighted(t, y, w, Nt, (Moments *)(base + o_mom), n_mom, stats, rec, refine_count, s);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
     PgramArgs a;
     a.rec = rec;
@@ -885,6 +913,8 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     a.Pn = p;
     a.part = (float *)(base + o_part);
     a.splits = eff;
+    a.refine_list = (uint32_t *)(base + o_list);
+    a.refine_count = refine_count;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx().prof) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
@@ -966,6 +996,62 @@ lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out,
     hipError_t e = launch_normals(seed, stream_id, n, out, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "normals launch");
     return LSP_OK;
+}
+
+// ---- probes ------------------------------------------------------------------------
+
+static lsp_status probe_device()
+{
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    int dev = 0;
+    DeviceInfo *di = nullptr;
+    return device_info(&dev, &di);
+}
+
+lsp_status lsp_probe_sincos(const float *r, int64_t n, float *s, float *c, void *stream)
+{
+    g_last_error.clear();
+    if (n < 0 || (n > 0 && (!r || !s || !c))) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (n == 0) return LSP_OK;
+    lsp_status st = probe_device();
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_probe_sincos(r, n, s, c, (hipStream_t)stream);
+    return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
+}
+
+lsp_status lsp_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int32_t phase, float *phi,
+                           void *stream)
+{
+    g_last_error.clear();
+    if (n < 0 || (n > 0 && (!t || !f || !phi)) || !std::isfinite(t_ref) ||
+        (phase != LSP_PHASE_SPLIT && phase != LSP_PHASE_SPLIT32 && phase != LSP_PHASE_NAIVE)) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (n == 0) return LSP_OK;
+    lsp_status st = probe_device();
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_probe_phase(t, f, n, t_ref, phase, phi, (hipStream_t)stream);
+    return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
+}
+
+lsp_status lsp_probe_recurrence(const double *t, int64_t n, double t_ref, double f0, double step_df, int32_t M,
+                                float *c, float *s, void *stream)
+{
+    g_last_error.clear();
+    if (n < 0 || (n > 0 && (!t || !c || !s)) || !std::isfinite(t_ref) || !std::isfinite(f0) ||
+        !std::isfinite(step_df) || M < 1 || M > probe_recur_max() || n > ((int64_t)1 << 40) / M) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    if (n == 0) return LSP_OK;
+    lsp_status st = probe_device();
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_probe_recur(t, n, t_ref, f0, step_df, M, c, s, (hipStream_t)stream);
+    return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
 }
 
 lsp_status lsp_profile_enable(int32_t on)

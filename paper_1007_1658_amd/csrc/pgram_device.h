@@ -17,6 +17,31 @@ enum { TR_DIRECT = LSP_TRIG_DIRECT, TR_RECUR = LSP_TRIG_RECUR, TR_MFMA = LSP_TRI
 __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
 __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
 
+// An FP64 phase p (revolutions) reduced to p - rint(p), |.| <= 1/2, then
+// rounded to FP32: the reduction every split-phase path uses (Section 4.4
+// reduces by the nearest integer too, but in FP32).
+__device__ __forceinline__ float rev_reduce(double p) { return (float)(p - rint(p)); }
+
+// A time offset t' as the FP32 pair the records hold: th = fl32(t'),
+// tl = fl32(t' - th); th + tl in FP64 is t' to about 2^-48 relative.
+__device__ __forceinline__ void split_time(double tp, float &th, float &tl)
+{
+    th = (float)tp;
+    tl = (float)(tp - (double)th);
+}
+
+// (cos, sin) of the recurrence step angle 2 pi step_df t', reduced and
+// evaluated in FP64 once per sample, rounded to FP32.
+__device__ __forceinline__ void step_rotation(double step_df, double tp, float &rc, float &rs)
+{
+    double q = step_df * tp;  // revolutions of the step angle
+    q -= rint(q);
+    double sq, cq;
+    sincospi(2.0 * q, &sq, &cq);
+    rc = (float)cq;
+    rs = (float)sq;
+}
+
 // ---------------------------------------------------------------------------
 // Prep: moments of x (mean, population variance; Section 3 opening paragraph)
 // and the time range, then the per-sample records.
@@ -97,18 +122,15 @@ __device__ __forceinline__ void write_record(const Records &rec, int64_t j, doub
         rec.rs[j] = 0.0f;
         return;
     }
-    double tp = tj - s.t_ref;
-    float th = (float)tp;
-    float tl = (float)(tp - (double)th);
-    double q = step_df * tp;  // revolutions of the step angle
-    q -= rint(q);
-    double sq, cq;
-    sincospi(2.0 * q, &sq, &cq);
+    const double tp = tj - s.t_ref;
+    float th, tl, rc, rs;
+    split_time(tp, th, tl);
+    step_rotation(step_df, tp, rc, rs);
     rec.th[j] = th;
     rec.tl[j] = tl;
     rec.xv[j] = xv;
-    rec.rc[j] = (float)cq;
-    rec.rs[j] = (float)sq;
+    rec.rc[j] = rc;
+    rec.rs[j] = rs;
 }
 
 // ---------------------------------------------------------------------------
@@ -185,15 +207,16 @@ struct Freq {
     static constexpr int N = (TRIG == TR_DIRECT) ? M : 1;
     double f[N];
     float fh[N], fl[N];
+    __device__ __forceinline__ void set(int m, double fm)
+    {
+        f[m] = fm;
+        fh[m] = (float)fm;
+        fl[m] = (float)(fm - (double)fh[m]);
+    }
     __device__ __forceinline__ void init(double f_min, double df, int64_t k)
     {
 #pragma unroll
-        for (int m = 0; m < N; ++m) {
-            double fm = f_min + (double)(k + (int64_t)kWave * m) * df;
-            f[m] = fm;
-            fh[m] = (float)fm;
-            fl[m] = (float)(fm - (double)fh[m]);
-        }
+        for (int m = 0; m < N; ++m) set(m, f_min + (double)(k + (int64_t)kWave * m) * df);
     }
 };
 
@@ -208,8 +231,7 @@ template <int PHASE, int TRIG, int M>
 __device__ __forceinline__ float phase_of(const Freq<PHASE, TRIG, M> &F, int m, const Smp &s)
 {
     if constexpr (PHASE == PH_SPLIT) {
-        double p = F.f[m] * s.t;
-        return (float)(p - rint(p));
+        return rev_reduce(F.f[m] * s.t);
     } else if constexpr (PHASE == PH_SPLIT32) {
         // (fh + fl)(th + tl) with fh*th carried exactly: p + e = fh*th
         float p = F.fh[m] * s.th;
@@ -233,32 +255,41 @@ __device__ __forceinline__ void acc_term(float (&p)[4][M], int m, float x, float
     p[3][m] = __builtin_fmaf(c, s, p[3][m]);  // CS
 }
 
+// (cos, sin) of 2 pi (f_0 + m S) t' for m = 0 .. M-1, handed to use(m, c, s):
+// hardware sin/cos of the seed phase ph (of f_0), one rotation by the step
+// (rc, rs) = (cos, sin)(2 pi S t'), then the three-term recurrence
+// c_{m+1} = 2 rc c_m - c_{m-1} (and likewise s).
+template <int M, class Use>
+__device__ __forceinline__ void recur_terms(float ph, float rc, float rs, Use &&use)
+{
+    float c0 = cos_rev(ph), s0 = sin_rev(ph);
+    use(0, c0, s0);
+    if constexpr (M > 1) {
+        float c1 = __builtin_fmaf(c0, rc, -(s0 * rs));
+        float s1 = __builtin_fmaf(s0, rc, c0 * rs);
+        use(1, c1, s1);
+        const float k2 = rc + rc;
+#pragma unroll
+        for (int m = 2; m < M; ++m) {
+            float c2 = __builtin_fmaf(k2, c1, -c0);
+            float s2 = __builtin_fmaf(k2, s1, -s0);
+            use(m, c2, s2);
+            c0 = c1;
+            c1 = c2;
+            s0 = s1;
+            s1 = s2;
+        }
+    }
+}
+
 // all M terms of one sample for this lane
 template <int PHASE, int TRIG, int M>
 __device__ __forceinline__ void sample_terms(float (&p)[4][M], const Freq<PHASE, TRIG, M> &F,
                                              const Smp &s)
 {
     if constexpr (TRIG == TR_RECUR) {
-        float ph = phase_of<PHASE, TRIG, M>(F, 0, s);
-        float c0 = cos_rev(ph), s0 = sin_rev(ph);
-        acc_term<M>(p, 0, s.x, c0, s0);
-        if constexpr (M > 1) {
-            // one exact rotation by the step angle, then the three-term recurrence
-            float c1 = __builtin_fmaf(c0, s.rc, -(s0 * s.rs));
-            float s1 = __builtin_fmaf(s0, s.rc, c0 * s.rs);
-            acc_term<M>(p, 1, s.x, c1, s1);
-            const float k2 = s.rc + s.rc;
-#pragma unroll
-            for (int m = 2; m < M; ++m) {
-                float c2 = __builtin_fmaf(k2, c1, -c0);
-                float s2 = __builtin_fmaf(k2, s1, -s0);
-                acc_term<M>(p, m, s.x, c2, s2);
-                c0 = c1;
-                c1 = c2;
-                s0 = s1;
-                s1 = s2;
-            }
-        }
+        recur_terms<M>(phase_of<PHASE, TRIG, M>(F, 0, s), s.rc, s.rs,
+                       [&](int m, float c, float sn) { acc_term<M>(p, m, s.x, c, sn); });
     } else {
 #pragma unroll
         for (int m = 0; m < M; ++m) {

@@ -135,16 +135,17 @@ __global__ void __launch_bounds__(256) prep_records_w_kernel(const double *__res
                                                              const float *__restrict__ y,
                                                              const float *__restrict__ w, int64_t Nt,
                                                              const Moments *__restrict__ part, int n_part,
-                                                             CurveStats *__restrict__ st, Records rec)
+                                                             CurveStats *__restrict__ st, Records rec,
+                                                             uint32_t *__restrict__ refine_count)
 {
     const CurveStats s = stats_of(merge_parts(part, n_part), (int)PH_SPLIT);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *st = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *st = s;
+        if (refine_count) *refine_count = 0u;  // the merge lists ill-conditioned bins from here on
+    }
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < Nt; j += stride) {
-        const double tp = t[j] - s.t_ref;
-        const float th = (float)tp;
-        rec.th[j] = th;
-        rec.tl[j] = (float)(tp - (double)th);
+        split_time(t[j] - s.t_ref, rec.th[j], rec.tl[j]);
         const double wn = (s.wsum > 0.0) ? (w ? (double)w[j] : 1.0) / s.wsum : 0.0;
         rec.xv[j] = (float)(wn * ((double)y[j] - s.mean));
         rec.wv[j] = (float)wn;
@@ -152,11 +153,12 @@ __global__ void __launch_bounds__(256) prep_records_w_kernel(const double *__res
 }
 
 hipError_t launch_prep_weighted(const double *t, const float *y, const float *w, int64_t Nt, Moments *moments,
-                                int n_moment_blocks, CurveStats *stats, Records rec, hipStream_t s)
+                                int n_moment_blocks, CurveStats *stats, Records rec, uint32_t *refine_count,
+                                hipStream_t s)
 {
     hipLaunchKernelGGL(prep_moments_w_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, y, w, Nt, moments);
     hipLaunchKernelGGL(prep_records_w_kernel, dim3(record_blocks(Nt)), dim3(256), 0, s, t, y, w, Nt,
-                       (const Moments *)moments, n_moment_blocks, stats, rec);
+                       (const Moments *)moments, n_moment_blocks, stats, rec, refine_count);
     return hipGetLastError();
 }
 

@@ -233,9 +233,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
             halfx8 v[R_KINDS];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                double p = bdf * S.t[8 * g + i];
-                p -= rint(p);
-                const float ph = (float)p;
+                const float ph = rev_reduce(bdf * S.t[8 * g + i]);
                 const float c = cos_rev(ph), s = sin_rev(ph);
                 float c2, s2;
                 double_angle(c, s, kTrigScale, c2, s2);
@@ -256,9 +254,7 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
             COp L, L2, LW;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                double p = Fa * S.t[js + i];
-                p -= rint(p);
-                const float ph = (float)p;
+                const float ph = rev_reduce(Fa * S.t[js + i]);
                 const float c = cos_rev(ph), s = sin_rev(ph);
                 const float xv = S.x[js + i];
                 L.set(i, xv * c, xv * s);
@@ -449,9 +445,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 halfx8 v[R_KINDS];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    double p = bdf * S.t[8 * g + i];
-                    p -= rint(p);
-                    const float ph = (float)p;
+                    const float ph = rev_reduce(bdf * S.t[8 * g + i]);
                     const float c = cos_rev(ph), s = sin_rev(ph);
                     float c2, s2;
                     double_angle(c, s, kTrigScale, c2, s2);
@@ -472,9 +466,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 COp L, L2;
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
-                    double p = Fa * S.t[js + i];
-                    p -= rint(p);
-                    const float ph = (float)p;
+                    const float ph = rev_reduce(Fa * S.t[js + i]);
                     const float c = cos_rev(ph), s = sin_rev(ph);
                     const float xv = S.x[js + i];
                     L.set(i, xv * c, xv * s);
@@ -570,36 +562,57 @@ hipError_t launch_batch_mfma(const BatchArgs &a, int persistent_blocks, hipStrea
     return hipGetLastError();
 }
 
-// FP64 merge of the six chunk sums and the generalized power (Section 6.3):
+// ---------------------------------------------------------------------------
+// The weighted least-squares powers from their sums (weights normalized to 1).
+//
+// A bin whose smallest pivot of the centred normal equations (for K = 1 the
+// smaller eigenvalue of the 2x2 system) falls below kRefinePivot is listed by
+// the merge and recomputed in FP64 (mh_refine_kernel): the FP32 chunk sums
+// carry absolute errors of a few 1e-7, which a pivot of 1e-2 turns into a few
+// 1e-5 of p at most, while near f = 0 (less than a cycle over the baseline)
+// or at aliases of the sampling the pivot falls far lower.
+constexpr double kRefinePivot = 1e-2;
+
+// Generalized power (Section 6.3's pointer to Zechmeister & Kuerster):
 //   CC = sum w cos^2 - C^2, SS = sum w sin^2 - S^2, CS = sum w cos sin - C S,
 //   p = (SS YC^2 + CC YS^2 - 2 CS YC YS) / (YY (CC SS - CS^2)),
-// with sum w cos^2 = (1 + Re)/2, sum w sin^2 = 1 - that, sum w cos sin = Im/2
-// (weights normalized to 1).  The FP32 chunk sums carry absolute errors of a
-// few 1e-7, so a direction with CC or SS <= 1e-5 counts as degenerate (f near
-// 0): the fit falls back to the other direction alone, else p = 0.
+// with sum w cos^2 = (1 + C2)/2, sum w sin^2 = (1 - C2)/2, sum w cos sin = S2/2
+// (C2 + i S2 = sum w e^{2i wt}).  A degenerate direction falls back to the
+// one-dimensional fit on the other, else p = 0.  FP32-derived sums: a
+// direction with CC or SS <= 1e-5 (or a determinant <= 1e-10) is degenerate;
+// FP64 sums (fp64 = true): the determinant or the direction <= 1e-12, the
+// oracle's rule.  *lmin: the smaller eigenvalue of [[CC, CS], [CS, SS]].
+__device__ __forceinline__ double gls_power(double C, double Sn, double YC, double YS, double C2, double S2,
+                                            double YY, bool fp64, double *lmin)
+{
+    const double CCh = 0.5 + 0.5 * C2, CSh = 0.5 * S2;
+    const double CC = CCh - C * C, SS = (1.0 - CCh) - Sn * Sn, CS = CSh - C * Sn;
+    const double D = CC * SS - CS * CS;
+    const double h = 0.5 * (CC - SS);
+    *lmin = 0.5 * (CC + SS) - sqrt(h * h + CS * CS);
+    if (!(YY > 0.0)) return 0.0;
+    const double eps = fp64 ? 1e-12 : 1e-5;
+    const bool two = fp64 ? (D > 1e-12) : (CC > eps && SS > eps && D > eps * eps);
+    if (two) return (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
+    if (CC > eps) return YC * YC / (YY * CC);
+    if (SS > eps) return YS * YS / (YY * SS);
+    return 0.0;
+}
+
+// FP64 merge of the six chunk sums (slots C, S, YC, YS, C2/2, S2/2) and the
+// generalized power; ill-conditioned bins are listed for the FP64 recomputation.
 __global__ void __launch_bounds__(256) gls_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
-                                                         const CurveStats *__restrict__ st, float *__restrict__ P)
+                                                         const CurveStats *__restrict__ st, float *__restrict__ P,
+                                                         uint32_t *__restrict__ list, uint32_t *__restrict__ count)
 {
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (k >= Nf) return;
     double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     sum_chunks<6, 4>(part, splits, Nf, k, v);
-    const double C = v[0], Sn = v[1], YC = v[2], YS = v[3];
-    const double CCh = 0.5 + v[4], CSh = v[5];
-    const double CC = CCh - C * C, SS = (1.0 - CCh) - Sn * Sn, CS = CSh - C * Sn;
-    const double D = CC * SS - CS * CS;
     const double YY = st->var;
-    double p = 0.0;
-    const double eps = 1e-5;
-    if (YY > 0.0) {
-        if (CC > eps && SS > eps && D > eps * eps)
-            p = (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
-        else if (CC > eps)
-            p = YC * YC / (YY * CC);
-        else if (SS > eps)
-            p = YS * YS / (YY * SS);
-    }
-    P[k] = (float)p;
+    double lmin;
+    P[k] = (float)gls_power(v[0], v[1], v[2], v[3], 2.0 * v[4], 2.0 * v[5], YY, false, &lmin);
+    if (YY > 0.0 && !(lmin >= kRefinePivot)) list[atomicAdd(count, 1u)] = (uint32_t)k;
 }
 
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
@@ -613,8 +626,10 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gls_reduce_kernel, dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
-                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn);
-    return hipGetLastError();
+                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn, a.refine_list, a.refine_count);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_refine(a, 1, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -800,9 +815,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
             halfx8 v[4 * P::NR];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                double p = bdf * S.t[8 * g + i];
-                p -= rint(p);
-                const float ph = (float)p;
+                const float ph = rev_reduce(bdf * S.t[8 * g + i]);
                 const float c1 = cos_rev(ph), s1 = sin_rev(ph);
                 MhRBuild<P, 1>::run(c1, s1, c1, s1, v, i);
             }
@@ -816,9 +829,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
             float e1r[8], e1i[8], er[8], ei[8], xv[8], wv[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                double p = Fa * S.t[js + i];
-                p -= rint(p);
-                const float ph = (float)p;
+                const float ph = rev_reduce(Fa * S.t[js + i]);
                 e1r[i] = cos_rev(ph);
                 e1i[i] = sin_rev(ph);
                 er[i] = e1r[i];
@@ -849,25 +860,22 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
     }
 }
 
-// FP64 merge and the least-squares solve.  Columns u = (cos hwt, sin hwt),
-// h = 1..K, centred by their weighted means (the constant is fitted):
+// The multi-harmonic power from the sums v (C_m, S_m for m = 1..2K at
+// v[2(m-1)], v[2(m-1)+1]; YC_h, YS_h for h = 1..K at v[4K + 2(h-1)], +1).
+// Columns u = (cos hwt, sin hwt), h = 1..K, centred by their weighted means
+// (the constant is fitted):
 //   G_ik = sum w u_i u_k - mean_i mean_k,  b_i = sum w (y - Y) u_i,
 // with sum w cos(Aw t) cos(Bw t) = (C_{A-B} + C_{A+B})/2 and the like
 // (C_0 = 1, S_0 = 0, C_{-m} = C_m, S_{-m} = -S_m).  Cholesky (in place, lower
-// triangle) with column dropping (a pivot <= 1e-5 of its diagonal, or a
-// diagonal <= 1e-5: columns the FP32 sums cannot separate);
-// p = |L^{-1} b|^2 / YY.
+// triangle) with column dropping; p = |L^{-1} b|^2 / YY.  FP32-derived sums:
+// a column whose centred diagonal or pivot is <= 1e-5 (of that diagonal) is
+// dropped (columns the FP32 sums cannot separate); FP64 sums (fp64 = true): a
+// pivot <= 1e-12 of the uncentred diagonal sum w u_i^2, the oracle's rule.
+// *min_pivot: the smallest pivot met (dropped columns included).
 template <int K>
-__global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
-                                                        const CurveStats *__restrict__ st, float *__restrict__ P)
+__device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64, double *min_pivot)
 {
-    constexpr int M2 = 2 * K, NS = 3 * K, n = 2 * K;
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= Nf) return;
-    double v[2 * NS];
-#pragma unroll
-    for (int q = 0; q < 2 * NS; ++q) v[q] = 0.0;
-    sum_chunks<2 * NS, (2 * NS >= 24 ? 1 : 2)>(part, splits, Nf, k, v);
+    constexpr int M2 = 2 * K, n = 2 * K;
     double C[M2 + 1], Sn[M2 + 1];
     C[0] = 1.0;
     Sn[0] = 0.0;
@@ -879,7 +887,7 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
     auto Cm = [&](int m) { return C[m < 0 ? -m : m]; };
     auto Sm = [&](int m) { return m < 0 ? -Sn[-m] : Sn[m]; };
     // column i: harmonic 1 + i/2, cos for even i, sin for odd i
-    double G[n][n], b[n], mean[n];
+    double G[n][n], b[n], mean[n], raw[n];
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const int h = 1 + i / 2;
@@ -891,16 +899,18 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
             const int A = 1 + i / 2, B = 1 + j / 2;
-            double raw;
-            if (i % 2 == 0 && j % 2 == 0) raw = 0.5 * (Cm(A - B) + Cm(A + B));
-            else if (i % 2 == 1 && j % 2 == 1) raw = 0.5 * (Cm(A - B) - Cm(A + B));
-            else if (i % 2 == 0) raw = 0.5 * (Sm(A + B) - Sm(A - B));  // cos(A) sin(B)
-            else raw = 0.5 * (Sm(A + B) + Sm(A - B));                   // sin(A) cos(B)
-            G[i][j] = raw - mean[i] * mean[j];
+            double r;
+            if (i % 2 == 0 && j % 2 == 0) r = 0.5 * (Cm(A - B) + Cm(A + B));
+            else if (i % 2 == 1 && j % 2 == 1) r = 0.5 * (Cm(A - B) - Cm(A + B));
+            else if (i % 2 == 0) r = 0.5 * (Sm(A + B) - Sm(A - B));  // cos(A) sin(B)
+            else r = 0.5 * (Sm(A + B) + Sm(A - B));                   // sin(A) cos(B)
+            if (i == j) raw[i] = r;
+            G[i][j] = r - mean[i] * mean[j];
         }
     const double eps = 1e-5;
     double z[n];
     double explained = 0.0;
+    double mp = INFINITY;
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         // G[i][0..i-1] already hold L[i][0..i-1] (zero for dropped columns)
@@ -908,8 +918,10 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
         double d = gii;
 #pragma unroll
         for (int c = 0; c < i; ++c) d -= G[i][c] * G[i][c];
+        mp = fmin(mp, d);
         z[i] = 0.0;
-        if (!(gii > eps) || !(d > eps * gii)) {
+        const bool drop = fp64 ? (!(raw[i] > 0.0) || !(d > 1e-12 * raw[i])) : (!(gii > eps) || !(d > eps * gii));
+        if (drop) {
 #pragma unroll
             for (int r = i + 1; r < n; ++r) G[r][i] = 0.0;  // column dropped
             continue;
@@ -928,8 +940,108 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
         z[i] = t / lii;
         explained += z[i] * z[i];
     }
+    *min_pivot = mp;
+    return (YY > 0.0) ? explained / YY : 0.0;
+}
+
+// FP64 merge of the 6K chunk sums and the least-squares solve; ill-conditioned
+// bins are listed for the FP64 recomputation.
+template <int K>
+__global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict__ part, int splits, int64_t Nf,
+                                                        const CurveStats *__restrict__ st, float *__restrict__ P,
+                                                        uint32_t *__restrict__ list, uint32_t *__restrict__ count)
+{
+    constexpr int NS = 3 * K;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= Nf) return;
+    double v[2 * NS];
+#pragma unroll
+    for (int q = 0; q < 2 * NS; ++q) v[q] = 0.0;
+    sum_chunks<2 * NS, (2 * NS >= 24 ? 1 : 2)>(part, splits, Nf, k, v);
     const double YY = st->var;
-    P[k] = (YY > 0.0) ? (float)(explained / YY) : 0.0f;
+    double piv;
+    P[k] = (float)mh_power<K>(v, YY, false, &piv);
+    if (YY > 0.0 && !(piv >= kRefinePivot)) list[atomicAdd(count, 1u)] = (uint32_t)k;
+}
+
+// FP64 recomputation of the listed bins, one workgroup per bin: each thread
+// sums samples tid, tid + 256, ... from the records the matrix-core kernels
+// read (t' = th + tl, w/W, w (y - Y)/W), with the phase reduced and the sine
+// and cosine evaluated in FP64 and the harmonics by complex products; a
+// fixed-order tree adds the threads' sums (the value of a bin does not depend
+// on which workgroup takes it), then the solve runs with the FP64 rule.
+template <int K>
+__global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
+{
+    constexpr int NV = 6 * K;
+    __shared__ double red[NV][256];
+    const int tid = threadIdx.x;
+    const uint32_t n = *a.refine_count;
+    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t k = (int64_t)a.refine_list[i];
+        const double f = a.f_min + (double)k * a.df;
+        double v[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) v[q] = 0.0;
+        for (int64_t j = tid; j < a.Nt; j += 256) {
+            const double tp = (double)a.rec.th[j] + (double)a.rec.tl[j];
+            double ph = f * tp;
+            ph -= rint(ph);
+            double s1, c1;
+            sincospi(2.0 * ph, &s1, &c1);
+            const double w = (double)a.rec.wv[j], y = (double)a.rec.xv[j];
+            double cr = c1, ci = s1;
+#pragma unroll
+            for (int m = 1; m <= 2 * K; ++m) {
+                if (m > 1) {
+                    const double r = cr * c1 - ci * s1;
+                    ci = cr * s1 + ci * c1;
+                    cr = r;
+                }
+                v[2 * (m - 1)] += w * cr;
+                v[2 * (m - 1) + 1] += w * ci;
+                if (m <= K) {
+                    v[4 * K + 2 * (m - 1)] += y * cr;
+                    v[4 * K + 2 * (m - 1) + 1] += y * ci;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) red[q][tid] = v[q];
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (tid < w) {
+#pragma unroll
+                for (int q = 0; q < NV; ++q) red[q][tid] += red[q][tid + w];
+            }
+            __syncthreads();
+        }
+        if (tid == 0) {
+#pragma unroll
+            for (int q = 0; q < NV; ++q) v[q] = red[q][0];
+            const double YY = a.stats->var;
+            double d;
+            const double p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d)
+                                      : mh_power<K>(v, YY, true, &d);
+            a.Pn[k] = (float)p;
+        }
+        __syncthreads();  // red is reused by the next bin
+    }
+}
+
+// the refinement pass: one workgroup per CU at most; workgroups past the
+// list's length (read on the device) exit at once
+hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s)
+{
+    const dim3 g((unsigned)(a.Nf < 256 ? a.Nf : 256)), b(256);
+    switch (K) {
+    case 1: hipLaunchKernelGGL(mh_refine_kernel<1>, g, b, 0, s, a); break;
+    case 2: hipLaunchKernelGGL(mh_refine_kernel<2>, g, b, 0, s, a); break;
+    case 3: hipLaunchKernelGGL(mh_refine_kernel<3>, g, b, 0, s, a); break;
+    case 4: hipLaunchKernelGGL(mh_refine_kernel<4>, g, b, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <int K>
@@ -954,8 +1066,10 @@ static hipError_t launch_mh_k(const PgramArgs &a, int waves, hipStream_t s, hipE
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mh_reduce_kernel<K>), dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
-                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn);
-    return hipGetLastError();
+                       (const float *)a.part, a.splits, a.Nf, a.stats, a.Pn, a.refine_list, a.refine_count);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_refine(a, K, s);
 }
 
 hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)

@@ -70,6 +70,11 @@ int main()
     EXPECT(lsp_normals(1, 0, -1, fake_f, nullptr) == LSP_ERR_INVALID_ARG);
     double ops = 0;
     EXPECT(lsp_microbench(42, 2, 10, nullptr, &ops, nullptr) == LSP_ERR_INVALID_ARG);
+    EXPECT(lsp_probe_sincos(nullptr, 4, fake_f, fake_f, nullptr) == LSP_ERR_INVALID_ARG);
+    EXPECT(lsp_probe_phase(fake_d, fake_d, 4, NAN, 0, fake_f, nullptr) == LSP_ERR_INVALID_ARG);
+    EXPECT(lsp_probe_recurrence(fake_d, 4, 0.0, 1.0, 0.1, 33, fake_f, fake_f, nullptr) == LSP_ERR_INVALID_ARG);
+    EXPECT(lsp_probe_recurrence(fake_d, (int64_t)1 << 40, 0.0, 1.0, 0.1, 32, fake_f, fake_f, nullptr) ==
+           LSP_ERR_INVALID_ARG);
     std::printf("validation: ok\n");
 
     // host helpers over wide ranges (no crash, finite or NaN as documented)

@@ -186,3 +186,20 @@ def test_microbench_validation_on_host():
     for kind, waves, iters in ((-1, 2, 10), (9, 2, 10), (4, 0, 10), (4, 9, 10), (4, 2, 0)):
         assert L.lsp_microbench(kind, waves, iters, null, ctypes.byref(ops), None) == lsp.LSP_ERR_INVALID_ARG
     assert L.lsp_microbench(4, 2, 10, null, None, None) == lsp.LSP_ERR_INVALID_ARG
+
+
+def test_probe_validation_on_host():
+    L = lsp.lib()
+    fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation rejects first
+    null = ctypes.c_void_p(0)
+    assert L.lsp_probe_sincos(fake, -1, fake, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_sincos(null, 5, fake, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_sincos(null, 0, null, null, null) == lsp.LSP_OK           # empty: nothing to do
+    assert L.lsp_probe_phase(fake, fake, 4, 0.0, 9, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_phase(fake, fake, 4, float("inf"), 0, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_phase(fake, null, 4, 0.0, 0, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    for M in (0, 33):
+        assert L.lsp_probe_recurrence(fake, 4, 0.0, 1.0, 0.1, M, fake, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_recurrence(fake, 4, 0.0, float("nan"), 0.1, 8, fake, fake, null) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_probe_recurrence(fake, 4, 0.0, 1.0, 0.1, 8, null, fake, null) == lsp.LSP_ERR_INVALID_ARG
+

@@ -67,3 +67,22 @@ def test_fast_rejects_offgrid_fmin():
     with pytest.raises(lsp.LspError) as ei:
         lsp.lsp_periodogram_fast(t, x, 0.5 * c.df, c.df, 10)
     assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("macc", [4, 8])
+def test_fast_reruns_are_bitwise_equal(macc):
+    """The spreading sums in fixed point, so the order in which the atomic
+    updates land cannot change a bit: reruns (with other work in between) and a
+    second stream give the same output."""
+    c = synth.c1()
+    t, x = _dev(c)
+    first = lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=macc)
+    for r in range(3):
+        _ = torch.ones(1 << 20, device="cuda").sum().item()
+        again = lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=macc)
+        assert torch.equal(again, first), r
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        other = lsp.lsp_periodogram_fast(t, x, c.f_min, c.df, c.Nf, macc=macc, stream=s)
+    s.synchronize()
+    assert torch.equal(other, first)

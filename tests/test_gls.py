@@ -117,3 +117,31 @@ def test_gls_long_series_sampled():
     print(f"gls long sampled rel err {err:.3e}", flush=True)
     assert err <= REL_TOL
     assert abs((kpk + 1) * df - 1.3) <= 1.5 * df
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_weighted_fit_on_degenerate_bins_every_bin(K):
+    """Even sampling on a grid from f = 0 past the Nyquist frequency, where the
+    sine columns vanish (f = 0, Nyquist/h) and the normal equations are
+    ill-conditioned around them: the merge hands those bins to the FP64
+    recomputation; every bin against the oracle, and reruns bitwise equal."""
+    g = np.random.default_rng([41, K])
+    N, dt = 600, 0.01
+    t = np.arange(N) * dt + 3.0
+    y = (1.5 + np.sin(2 * np.pi * 7.3 * t) + 0.4 * np.cos(2 * np.pi * 14.6 * t) + g.normal(0, 0.7, N)).astype(np.float32)
+    w = g.uniform(0.5, 2.0, N).astype(np.float32)
+    df = 1.0 / (4 * (t[-1] - t[0]))
+    Nf = int(1.2 * (0.5 / dt) / df)
+    td, yd, wd = _dev(t, y, w)
+    if K == 1:
+        P = oracle.gls(t, y.astype(np.float64), 0.0, df, Nf=Nf, w=w.astype(np.float64))
+        run = lambda: lsp.lsp_gls(td, yd, 0.0, df, Nf, w=wd)
+    else:
+        P = oracle.multiharmonic(t, y.astype(np.float64), K, 0.0, df, Nf=Nf, w=w.astype(np.float64))
+        run = lambda: lsp.lsp_multiharmonic(td, yd, K, 0.0, df, Nf, w=wd)
+    Pg = run()
+    err = rel_err(Pg.cpu().numpy(), P)
+    print(f"degenerate-bin sweep K={K} Nf={Nf}: every-bin rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert peak_matches(Pg.cpu().numpy(), P)
+    assert torch.equal(run(), Pg)

@@ -21,25 +21,6 @@ def _dev(*arrs):
     return [None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
 
 
-def _well_conditioned(t, w, fs, limit=1e3, K=2):
-    """Bins whose centred Gram matrix of (cos, sin)(h w t), h = 1..K, has a
-    condition number <= limit.  The GPU forms the normal equations from FP32
-    sums, so its error grows with that number: below about half a cycle per
-    baseline (the first bin or two of an oversampling-4 grid) the fit is
-    ill-conditioned and only the range [0, 1] is asserted there."""
-    w = np.ones_like(t) if w is None else w.astype(np.float64)
-    w = w / w.sum()
-    tc = t - 0.5 * (t[0] + t[-1])
-    ok = []
-    for f in fs:
-        th = 2 * np.pi * f * tc
-        U = np.stack([fn(h * th) for h in range(1, K + 1) for fn in (np.cos, np.sin)], 1)
-        m = w @ U
-        G = (U * w[:, None]).T @ U - np.outer(m, m)
-        ok.append(np.linalg.cond(G) <= limit)
-    return np.array(ok)
-
-
 def _case(Nt, seed, weighted):
     g = np.random.default_rng([29, Nt, seed])
     t = np.sort(g.uniform(0.0, 30.0, Nt))
@@ -55,20 +36,21 @@ def _case(Nt, seed, weighted):
 @pytest.mark.parametrize("weighted", [False, True])
 @pytest.mark.parametrize("K", [2, 3, 4])
 def test_multiharmonic_matches_oracle(Nt, Nf, splits, weighted, K):
+    """Every bin, including the lowest (less than a cycle over the baseline,
+    where the centred normal equations are ill-conditioned and the merge hands
+    the bin to the FP64 recomputation) and Nt = 2K + 1 (as many samples as
+    parameters: the fit interpolates)."""
     print(f"mh K={K} Nt={Nt} Nf={Nf} splits={splits} weighted={weighted}", flush=True)
-    if Nt < 2 * K + 3:
-        pytest.skip("as many samples as parameters: the fit interpolates and the Gram matrix is "
-                    "ill-conditioned at most bins")
     t, y, w = _case(Nt, 1, weighted)
     df = 1.0 / (4 * (t[-1] - t[0]))
     P = oracle.multiharmonic(t, y.astype(np.float64), K, df, df, Nf=Nf,
                              w=None if w is None else w.astype(np.float64))
     td, yd, wd = _dev(t, y, w)
     Pg = lsp.lsp_multiharmonic(td, yd, K, df, df, Nf, w=wd, splits=splits).cpu().numpy()
-    good = _well_conditioned(t, w, df + np.arange(Nf) * df, K=K)
-    assert good.mean() >= 0.7
-    assert np.max(np.abs(Pg[good] - P[good])) <= REL_TOL * P.max()
-    assert peak_matches(np.where(good, Pg, 0), np.where(good, P, 0))
+    err = rel_err(Pg, P)
+    print(f"mh K={K} Nt={Nt}: every-bin rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert peak_matches(Pg, P)
     assert np.all(Pg >= -1e-5) and np.all(Pg <= 1 + 1e-5)
 
 
@@ -84,17 +66,16 @@ def test_multiharmonic_full_size_sampled(K):
     k = np.unique(np.concatenate([g.integers(0, c.Nf, 150), np.arange(max(0, kpk - 6), min(c.Nf, kpk + 7)),
                                   np.arange(0, 16), np.arange(c.Nf - 16, c.Nf)]))
     P = oracle.multiharmonic(c.t, c.x.astype(np.float64), K, c.f_min, c.df, k=k, w=w.astype(np.float64))
-    good = _well_conditioned(c.t, w, c.f_min + k * c.df, K=K)
-    assert good.mean() >= 0.95
-    err = float(np.max(np.abs(Pg[k][good] - P[good])) / P.max())
-    print(f"mh K={K} c1 sampled rel err {err:.3e}", flush=True)
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
+    low = float(np.max(np.abs(Pg[:16] - P[:16])) / P.max())
+    print(f"mh K={K} c1 sampled rel err {err:.3e} (first 16 bins {low:.3e})", flush=True)
     assert err <= REL_TOL
 
 
 def test_multiharmonic_long_series_sampled():
     """K = 2 on 2^20 weighted samples: the records kernel (bounded grid, each
     block merging the moments itself) strides over them; oracle on sampled
-    well-conditioned bins."""
+    bins and the lowest eight."""
     Nt, Nf, K = 1 << 20, 2048, 2
     t, y, w = _case(Nt, 3, True)
     df = 1.0 / (4 * (t[-1] - t[0]))
@@ -103,11 +84,10 @@ def test_multiharmonic_long_series_sampled():
     Pg = lsp.lsp_multiharmonic(td, yd, K, df, df, Nf, w=wd).cpu().numpy()
     g = np.random.default_rng(12)
     kpk = int(np.argmax(Pg))
-    k = np.unique(np.concatenate([g.integers(0, Nf, 32), np.arange(max(0, kpk - 3), min(Nf, kpk + 4))]))
+    k = np.unique(np.concatenate([g.integers(0, Nf, 32), np.arange(max(0, kpk - 3), min(Nf, kpk + 4)),
+                                  np.arange(0, 8)]))
     P = oracle.multiharmonic(t, y.astype(np.float64), K, df, df, k=k, w=w.astype(np.float64))
-    good = _well_conditioned(t, w, df + k * df, K=K)
-    assert good.mean() >= 0.9
-    err = float(np.max(np.abs(Pg[k][good] - P[good])) / P.max())
+    err = float(np.max(np.abs(Pg[k] - P)) / P.max())
     print(f"mh long sampled rel err {err:.3e}", flush=True)
     assert err <= REL_TOL
     assert abs((kpk + 1) * df - 0.9) <= 1.5 * df

@@ -1,0 +1,144 @@
+"""Unit pins of the kernels' building blocks (needs a gfx950 GPU), each run
+through the probe entry points with the device code the kernels use and
+compared on the host with FP64 or 80-bit references:
+
+  * the hardware sine and cosine in revolutions over [-1/2, 1/2], every FP32
+    input with |r| >= 2^-14 (Section 4.4 quotes the maximum error of the
+    intrinsic the paper used: 2^-21.41 for sin, 2^-21.19 for cos);
+  * the reduced phase of the SPLIT and SPLIT32 modes over the (f, t')
+    ranges of the long and the epoch-offset workloads, against 80-bit long
+    double (bar 2e-6 revolutions), and the NAIVE mode beside them;
+  * the frequency recurrence, error per step m against long double.
+"""
+import numpy as np
+import pytest
+
+from paper_1007_1658_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1007_1658_amd as lsp  # noqa: E402
+
+TRIG_BOUND = 2.0 ** -19     # a few times the paper's 2^-21.2: far inside the 1e-4 Pn budget
+PHASE_BOUND = 2e-6          # revolutions
+
+
+def _binade(e, sign, stride=1):
+    """All FP32 values with |r| in [2^e, 2^(e+1)) (every stride-th mantissa)."""
+    m = np.arange(0, 1 << 23, stride, dtype=np.uint32)
+    bits = (np.uint32(e + 127) << np.uint32(23)) | m
+    if sign < 0:
+        bits |= np.uint32(1 << 31)
+    return bits.view(np.float32)
+
+
+def test_hardware_sincos_error_table():
+    rows = []
+    worst_s = worst_c = 0.0
+    for e in range(-30, -1):
+        stride = 1 if e >= -14 else 64
+        for sign in (1, -1):
+            r = _binade(e, sign, stride)
+            s, c = lsp.lsp_probe_sincos(torch.from_numpy(r).cuda())
+            a = 2.0 * np.pi * r.astype(np.float64)
+            es = float(np.max(np.abs(s.cpu().numpy().astype(np.float64) - np.sin(a))))
+            ec = float(np.max(np.abs(c.cpu().numpy().astype(np.float64) - np.cos(a))))
+            rows.append((e, sign, es, ec))
+            worst_s, worst_c = max(worst_s, es), max(worst_c, ec)
+    # the end points +-1/2
+    r = np.array([0.5, -0.5, 0.0], dtype=np.float32)
+    s, c = lsp.lsp_probe_sincos(torch.from_numpy(r).cuda())
+    a = 2.0 * np.pi * r.astype(np.float64)
+    worst_s = max(worst_s, float(np.max(np.abs(s.cpu().numpy() - np.sin(a)))))
+    worst_c = max(worst_c, float(np.max(np.abs(c.cpu().numpy() - np.cos(a)))))
+    for e, sign, es, ec in rows:
+        if e >= -14:
+            print(f"|r| in [2^{e}, 2^{e + 1}) sign {sign:+d}: max|dsin| = 2^{np.log2(max(es, 1e-300)):.2f}  "
+                  f"max|dcos| = 2^{np.log2(max(ec, 1e-300)):.2f}", flush=True)
+    print(f"sincos over [-1/2, 1/2] rev: max|dsin| = {worst_s:.3e} (2^{np.log2(worst_s):.2f}), "
+          f"max|dcos| = {worst_c:.3e} (2^{np.log2(worst_c):.2f})", flush=True)
+    assert worst_s <= TRIG_BOUND and worst_c <= TRIG_BOUND
+
+
+def _phase_pairs(curve, n, seed):
+    g = np.random.default_rng(seed)
+    j = g.integers(0, curve.Nt, n)
+    k = g.integers(0, curve.Nf, n)
+    # the corners of the (f, t') range
+    jt = np.array([int(np.argmin(curve.t)), int(np.argmax(curve.t))])
+    kt = np.array([0, curve.Nf - 1])
+    j = np.concatenate([j, np.repeat(jt, 2)])
+    k = np.concatenate([k, np.tile(kt, 2)])
+    t = curve.t[j]
+    f = curve.f_min + k.astype(np.float64) * curve.df
+    return t, f
+
+
+def _wrap(d):
+    return d - np.rint(d)
+
+
+@pytest.mark.parametrize("config", ["c1", "c2"])
+def test_phase_modes_against_long_double(config):
+    c = getattr(synth, config)()
+    t_ref = 0.5 * (float(c.t.min()) + float(c.t.max()))
+    t, f = _phase_pairs(c, 1 << 20, 31)
+    td, fd = torch.from_numpy(t).cuda(), torch.from_numpy(f).cuda()
+    tl, fl = t.astype(np.longdouble), f.astype(np.longdouble)
+    ref = _wrap(fl * (tl - np.longdouble(t_ref)))       # what SPLIT and SPLIT32 reduce
+    ref_raw = _wrap(fl * tl)                             # what NAIVE reduces (no time origin)
+    err = {}
+    for mode, r in (("split", ref), ("split32", ref), ("naive", ref_raw)):
+        phi = lsp.lsp_probe_phase(td, fd, t_ref, mode).cpu().numpy()
+        assert np.all(np.abs(phi) <= 0.5 + 1e-6), mode
+        err[mode] = float(np.max(np.abs(_wrap(phi.astype(np.longdouble) - r))))
+    span = float(np.max(np.abs(f * (t - t_ref))))
+    print(f"{config}: |f t'| <= {span:.3e} rev; max phase error split {err['split']:.3e}, "
+          f"split32 {err['split32']:.3e}, naive {err['naive']:.3e} rev", flush=True)
+    assert err["split"] <= PHASE_BOUND
+    assert err["split32"] <= PHASE_BOUND
+    if config == "c2":
+        assert err["naive"] > 100 * PHASE_BOUND   # FP32 cannot hold f t at ~1e8 revolutions
+
+
+def test_recurrence_error_per_step():
+    """The recurrence form's (cos, sin) of slots m = 0..31 against long double,
+    on the long workload's times, at low, middle and high seed frequencies:
+    the largest and the root-mean-square error over the samples, per m.
+
+    The three-term recurrence runs on 2 cos(theta) rounded to FP32, theta the
+    per-sample step angle; where theta is near 0 or pi that rounding moves the
+    effective angle by up to 2^-24 / |sin theta|, so a few samples carry per-term
+    errors that grow with m.  They enter the sums with weight 1/Nt and random
+    signs, which is why the end-to-end parity (every bin of the long workload,
+    per M) stays far inside the bar; the RMS is the figure that bounds it."""
+    c = synth.c1()
+    t_ref = 0.5 * (float(c.t.min()) + float(c.t.max()))
+    t = c.t[np.random.default_rng(5).choice(c.Nt, 8192, replace=False)]
+    step = 64.0 * c.df
+    M = 32
+    tl = (t.astype(np.longdouble) - np.longdouble(t_ref))[:, None]
+    worst = np.zeros(M)
+    sq = np.zeros(M)
+    n = 0
+    for k0 in (0, c.Nf // 3 + 7, c.Nf - 64 * M):
+        f0 = c.f_min + k0 * c.df
+        cg, sg = lsp.lsp_probe_recurrence(torch.from_numpy(t).cuda(), t_ref, f0, step, M)
+        fm = np.longdouble(f0) + np.arange(M, dtype=np.longdouble)[None, :] * np.longdouble(step)
+        a = 2 * np.pi * _wrap(fm * tl)
+        e = np.maximum(np.abs(cg.cpu().numpy() - np.cos(a)), np.abs(sg.cpu().numpy() - np.sin(a))).astype(np.float64)
+        worst = np.maximum(worst, e.max(axis=0))
+        sq += (e ** 2).sum(axis=0)
+        n += e.shape[0]
+    rms = np.sqrt(sq / n)
+    print("recurrence error per slot m (max / rms): " +
+          ", ".join(f"{m}:{worst[m]:.1e}/{rms[m]:.1e}" for m in range(M)), flush=True)
+    assert worst[0] <= TRIG_BOUND + 1e-7            # the seed: hardware sin/cos of the SPLIT phase
+    assert worst[1] <= 2 * TRIG_BOUND + 2e-7        # one rotation by the FP32 step
+    m = np.arange(M)
+    assert np.all(rms <= (m + 1) * 4e-6)
+    assert np.all(worst <= 0.05)                    # a wrong coefficient or sign gives O(1) errors
