@@ -427,9 +427,13 @@ int oracle_gls(const double *t, const double *y, const double *w_in, int64_t Nt,
    Here the fit is done literally: the (2K+1)-column weighted normal equations
    are formed in FP64 (Neumaier sums) and solved by Cholesky factorization;
    p_K = (explained sum of squares) / chi2_0 with normalized weights.  A
-   system whose Cholesky pivot falls to <= 1e-12 times its diagonal (columns
-   collinear: f = 0, or K f at a Nyquist-like frequency of the sampling) drops
-   that column, i.e. fits the remaining ones.  K in 1..4. */
+   column whose Cholesky pivot falls to <= 1e-12 of the total weight (the
+   constant column's diagonal, 1 here) drops out, i.e. the remaining ones are
+   fitted: collinear columns (f = 0) and columns that vanish (sin h w t at a
+   Nyquist-like frequency of the sampling, where only rounding is left).  This
+   is the absolute rule of the generalized periodogram above (and of the
+   degenerate denominators of Eq. (1)), so K = 1 is that periodogram on
+   every bin.  K in 1..4. */
 
 #define MH_MAXK 4
 #define MH_MAXC (2 * MH_MAXK + 1)
@@ -471,7 +475,7 @@ static double mh_one_frequency(const double *t, const double *y, const double *w
         double d = A[i][i];
         for (int k = 0; k < i; ++k)
             if (keep[k]) d -= L[i][k] * L[i][k];
-        if (!(d > 1e-12 * A[i][i]) || !(A[i][i] > 0.0)) {
+        if (!(d > 1e-12 * A[0][0]) || !(A[i][i] > 0.0)) {
             for (int k = 0; k <= i; ++k) L[i][k] = 0.0;
             z[i] = 0.0;
             continue;

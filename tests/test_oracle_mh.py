@@ -69,3 +69,38 @@ def test_mh_degenerate_zero_frequency_is_zero():
     y = g.normal(0, 1, 30)
     # f = 0: every harmonic column is the constant or zero; nothing beyond the mean is explained
     assert oracle.multiharmonic(t, y, 2, 0.0, 0.1, Nf=1)[0] == pytest.approx(0.0, abs=1e-12)
+
+
+def _reduced_lstsq_power(t, y, w, cols):
+    """Brute-force weighted fit of the constant plus the given columns."""
+    sw = np.sqrt(w)
+    A = np.stack([np.ones_like(t)] + cols, axis=1)
+    coef, *_ = np.linalg.lstsq(A * sw[:, None], y * sw, rcond=None)
+    chi2 = np.sum(w * (y - A @ coef) ** 2)
+    Y = np.sum(w * y) / np.sum(w)
+    return 1.0 - chi2 / np.sum(w * (y - Y) ** 2)
+
+
+@pytest.mark.parametrize("K", [2, 3])
+def test_mh_vanishing_columns_at_nyquist_drop_out(K):
+    """Even sampling at the Nyquist frequency: sin(w t_j) is zero up to the
+    rounding of the phase, and cos(2 w t_j) is the constant.  Such columns
+    carry no information and drop out (pivot <= 1e-12 of the total weight, the
+    rule of the generalized periodogram), so the power is the brute-force fit
+    of the columns that remain (cos w t, and for K = 3 cos 3wt = cos wt: only
+    one).  A rule relative to each column's own size would keep the rounding
+    noise of the sine column and fit it."""
+    g = np.random.default_rng([12, K])
+    N, dt = 200, 0.01
+    t = np.arange(N) * dt + 3.0
+    y = 1.5 + np.sin(2 * np.pi * 7.3 * t) + g.normal(0, 0.7, N)
+    w = g.uniform(0.5, 2.0, N)
+    fn = 0.5 / dt
+    p = oracle.multiharmonic(t, y, K, fn, 1.0, Nf=1, w=w)[0]
+    ref = _reduced_lstsq_power(t, y, w, [np.cos(np.pi * np.arange(N))])
+    assert p == pytest.approx(ref, rel=1e-9)
+    # one harmonic is the generalized periodogram on every bin of an even grid
+    # from f = 0 through the Nyquist frequency (degenerate bins included)
+    df = fn / 64
+    assert np.allclose(oracle.multiharmonic(t, y, 1, 0.0, df, Nf=70, w=w), oracle.gls(t, y, 0.0, df, Nf=70, w=w),
+                       rtol=1e-9, atol=1e-13)
