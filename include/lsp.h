@@ -296,7 +296,7 @@ lsp_status lsp_normals(uint64_t seed, uint64_t stream_id, int64_t n, float *out,
    GELU (tanh form) after the first three layers; products on BF16 matrix
    cores with FP32 accumulation.  With the exponential-equivalent power
    w(z) = -((Nt-3)/2) ln(1 - 2z/Nt) (a single frequency exceeds z with the
-   beta-law probability exp(-w), Section 2), the maximum is Gumbel in w:
+   beta-law probability exp(-w), Section 3), the maximum is Gumbel in w:
      P(max <= z) = exp(-exp(-u)),  u = (w(z) - ln Nf - m) / beta,
      m = mu + sigma r_0,  beta = softplus(r_1 + ln(e - 1)),
    so m = 0, beta = 1 is Eq. (3) with Nf independent frequencies.  Training

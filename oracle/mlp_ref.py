@@ -7,7 +7,7 @@ GELU is the tanh form 0.5 z (1 + tanh(sqrt(2/pi) (z + 0.044715 z^3))).
 
 The two outputs set the law of the maximum power of white noise over the
 pattern's grid.  A single frequency's power z exceeds a level with the
-probability of the beta law of Section 2, (1 - 2z/Nt)^((Nt-3)/2) = exp(-w(z)),
+probability of the beta law of Section 3, (1 - 2z/Nt)^((Nt-3)/2) = exp(-w(z)),
 w(z) = -((Nt-3)/2) ln(1 - 2z/Nt); the maximum is modelled as Gumbel in w,
   P(max <= z) = exp(-exp(-u)),  u = (w(z) - ln Nf - m) / beta,
   m = mu + sigma r_0,  beta = softplus(r_1 + ln(e - 1))   (beta = 1 at r_1 = 0),

@@ -125,6 +125,13 @@ SIGNATURES = {
 def load_library(path):
     """A libmi355lsp build at `path` with the C signatures declared (e.g. the
     LDS-poisoning debug build, debug/libmi355lsp_poison.so)."""
+    # torch first, where it is installed: its HIP runtime is then the one the
+    # library binds to (both are libamdhip64.so.7), so tensors and the
+    # library's calls share one runtime whichever the caller touched first
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(L, name)

@@ -1,8 +1,9 @@
 // mlp_kernels.hip -- the false-alarm surrogate's network on gfx950 matrix cores.
 //
-// A 4-layer perceptron (68 -> 256 -> 256 -> 256 -> 9, GELU in tanh form after
-// the first three layers) maps sampling-pattern features to nine quantiles of
-// the maximum periodogram power of white noise.  Products run on BF16 MFMA
+// A 4-layer perceptron (68 -> 256 -> 256 -> 256 -> 2, GELU in tanh form after
+// the first three layers) maps sampling-pattern features to the two parameters
+// (location and scale) of the law of the maximum periodogram power of white
+// noise; quantiles and false-alarm probabilities follow from that law.  Products run on BF16 MFMA
 // (v_mfma_f32_16x16x32_bf16) with FP32 accumulation; FP32 master weights,
 // Adam moments and all elementwise work stay in FP32.
 //
@@ -131,7 +132,7 @@ hipError_t launch_features_in(const float *feat, int B, int Bp, const float *mea
 // ---------------------------------------------------------------------------
 // The law of the maximum.  A single frequency's normalized power z exceeds a
 // level with the beta-law probability (1 - 2z/Nt)^((Nt-3)/2) = exp(-w(z)) of
-// white noise (Section 2, after Eq. (3)); the maximum over the grid is taken
+// white noise (Section 3, beside Eq. (3)); the maximum over the grid is taken
 // as Gumbel in w with location ln Nf + m and scale beta:
 //   P(max <= z) = exp(-exp(-u)),  u = (w(z) - ln Nf - m) / beta,
 //   m = mu + sigma r_0,  beta = softplus(r_1 + ln(e - 1)).

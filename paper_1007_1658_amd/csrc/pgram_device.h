@@ -233,15 +233,22 @@ __device__ __forceinline__ float phase_of(const Freq<PHASE, TRIG, M> &F, int m, 
     if constexpr (PHASE == PH_SPLIT) {
         return rev_reduce(F.f[m] * s.t);
     } else if constexpr (PHASE == PH_SPLIT32) {
-        // (fh + fl)(th + tl) with fh*th carried exactly: p + e = fh*th
+#pragma clang fp contract(off)
+        // (fh + fl)(th + tl) with fh*th carried exactly: p + e = fh*th (p the
+        // rounded product: no contraction of p into the subtractions).  The
+        // correction q (at most about half an ulp of p, ~1e-3 revolutions at
+        // |p| ~ 3e4) can carry r + q just past 1/2, so the sum is reduced once
+        // more (an exact subtraction of 0 or +-1).
         float p = F.fh[m] * s.th;
         float e = __builtin_fmaf(F.fh[m], s.th, -p);
         float r = p - __builtin_rintf(p);
         float q = __builtin_fmaf(F.fh[m], s.tl, e);
         q = __builtin_fmaf(F.fl[m], s.th, q);
-        return r + q;
+        const float v = r + q;
+        return v - __builtin_rintf(v);
     } else {
-        float ft = F.fh[m] * s.th;  // the paper's FP32 reduction
+#pragma clang fp contract(off)
+        float ft = F.fh[m] * s.th;  // the paper's FP32 reduction of the rounded product
         return ft - __builtin_rintf(ft);
     }
 }

@@ -970,10 +970,18 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 // and cosine evaluated in FP64 and the harmonics by complex products; a
 // fixed-order tree adds the threads' sums (the value of a bin does not depend
 // on which workgroup takes it), then the solve runs with the FP64 rule.
+// The records hold the normalized weights and centred values rounded to FP32,
+// so their own totals W0 = sum w/W and Y0 = sum w (y - Y)/W (summed alongside,
+// in the same order) differ from 1 and 0 by rounding: every weight sum is
+// divided by W0 and every value sum is centred on Y0/W0, which makes the
+// normal equations those of the records' own weights exactly (at f = 0 the
+// cosine sums then equal their weight total bit for bit, and the constant
+// direction is dropped as the oracle drops it).
 template <int K>
 __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
 {
-    constexpr int NV = 6 * K;
+    constexpr int NS = 6 * K;      // harmonic sums
+    constexpr int NV = NS + 2;     // and the records' weight and value totals
     __shared__ double red[NV][256];
     const int tid = threadIdx.x;
     const uint32_t n = *a.refine_count;
@@ -1005,6 +1013,8 @@ __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
                     v[4 * K + 2 * (m - 1) + 1] += y * ci;
                 }
             }
+            v[NS] += w;
+            v[NS + 1] += y;
         }
 #pragma unroll
         for (int q = 0; q < NV; ++q) red[q][tid] = v[q];
@@ -1019,10 +1029,17 @@ __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
         if (tid == 0) {
 #pragma unroll
             for (int q = 0; q < NV; ++q) v[q] = red[q][0];
+            const double W0 = v[NS], ybar = v[NS + 1] / W0;
+#pragma unroll
+            for (int q = 0; q < 4 * K; ++q) v[q] /= W0;
+#pragma unroll
+            for (int q = 0; q < 2 * K; ++q) v[4 * K + q] = v[4 * K + q] / W0 - ybar * v[q];
             const double YY = a.stats->var;
             double d;
-            const double p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d)
-                                      : mh_power<K>(v, YY, true, &d);
+            double p = 0.0;
+            if (W0 > 0.0)
+                p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d)
+                             : mh_power<K>(v, YY, true, &d);
             a.Pn[k] = (float)p;
         }
         __syncthreads();  // red is reused by the next bin

@@ -62,12 +62,31 @@ def test_param_roundtrip_and_count():
     m.close()
 
 
+def max_elem_rel(a, b, scale):
+    """max_i |a_i - b_i| / scale_i (element by element)"""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.max(np.abs(a - b) / scale))
+
+
+# Element-wise bars.  Both sides round the matrix-product operands to BF16 at
+# the same points; they differ by FP32 against FP64 accumulation, which can
+# flip the BF16 rounding of an activation (a 2^-8 relative step) and carry it
+# forward.  Quantiles: |dq| <= 2e-3 |q|.  Gradients: |dg| <= 2e-2 of the
+# largest |g| of the same layer's weights or biases (a per-layer scale, so a
+# wrong layout in one product cannot hide behind a large gradient elsewhere).
+Q_ELEM_TOL = 2e-3
+G_ELEM_TOL = 2e-2
+
+
 def test_forward_matches_reference():
     m, params, feat, y, mean, std = _model_and_data()
     q = m.forward(torch.from_numpy(feat).cuda()).cpu().numpy()
     for e in range(2):
         ref = R.forward(params[e].astype(np.float64), feat, mean, std, MU, SIGMA, bf=True)["q"]
-        assert rel_l2(q[e], ref) <= 1e-3
+        err = max_elem_rel(q[e], ref, np.abs(ref))
+        print(f"member {e}: quantiles max element rel err {err:.3e}, rel L2 {rel_l2(q[e], ref):.3e}", flush=True)
+        assert err <= Q_ELEM_TOL
         assert np.all(np.diff(q[e], axis=1) > 0)
     m.close()
 
@@ -79,11 +98,14 @@ def test_gradient_matches_reference():
     assert abs(loss.item() - Lr) <= 1e-4 * abs(Lr)
     gg = g.cpu().numpy()
     assert rel_l2(gg, gr) <= 1e-3
-    # per layer, so that a wrong layout in one product cannot hide in the total
+    # element by element, per layer's weights and biases
     o = 0
-    for (n_out, n_in) in R.SHAPES:
-        for sz in (n_out * n_in, n_out):
-            assert rel_l2(gg[o:o + sz], gr[o:o + sz]) <= 5e-3
+    for li, (n_out, n_in) in enumerate(R.SHAPES):
+        for what, sz in (("W", n_out * n_in), ("b", n_out)):
+            seg, ref = gg[o:o + sz], gr[o:o + sz]
+            err = max_elem_rel(seg, ref, np.abs(ref).max())
+            print(f"layer {li} {what}: max |dg| / max |g| = {err:.3e}", flush=True)
+            assert err <= G_ELEM_TOL
             o += sz
     m.close()
 

@@ -101,3 +101,18 @@ def test_head_scale_is_positive_and_gelu_grad_matches():
     z = np.linspace(-6, 6, 101)
     h = 1e-6
     assert np.allclose(R.gelu_grad(z), (R.gelu(z + h) - R.gelu(z - h)) / (2 * h), atol=1e-8)
+
+
+def test_gelu_matches_torch_tanh_form_and_erf_form():
+    """The tanh-form GELU against an independent implementation (torch's
+    approximate='tanh' on the CPU, in FP64), and against the exact erf form
+    it approximates (Hendrycks & Gimpel's tanh form is within 5e-4 of it): a
+    wrong constant in either the sqrt(2/pi) factor or the cubic coefficient
+    fails the first comparison."""
+    torch = pytest.importorskip("torch")
+    from scipy.special import erf
+    z = np.linspace(-8.0, 8.0, 4001)
+    ref = torch.nn.functional.gelu(torch.from_numpy(z), approximate="tanh").numpy()
+    assert np.max(np.abs(R.gelu(z) - ref)) <= 1e-14
+    exact = 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))
+    assert np.max(np.abs(R.gelu(z) - exact)) <= 5e-4
