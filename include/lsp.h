@@ -144,6 +144,30 @@ lsp_status lsp_periodogram_ex(const double *t, const float *x, int64_t Nt,
                               double f_min, double df, int64_t Nf, float *Pn,
                               void *stream, const lsp_options *opt);
 
+/* As lsp_periodogram, for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the workspace (sample records, curve statistics and per-chunk
+   sums) is a fixed array of LSP_NOALLOC_SCRATCH_BYTES that the library
+   holds in each GPU's memory until the process ends; no call allocates or
+   frees device memory.  The first call on a device (its set-up) looks up
+   that device's array address and caches device facts; later calls do no
+   host set-up either.  Default phase mode and launch shape, except that the
+   sample axis is split into no more chunks than the array holds sums for
+   (so results agree with lsp_periodogram to the library's tolerance, not
+   always bit for bit).
+   Size limit: 5 FP32 records per sample plus 4 FP32 sums per frequency
+   (about 20 Nt + 16 Nf bytes, plus alignment) must fit the array, else
+   LSP_ERR_INVALID_ARG before any GPU work, with the byte counts in
+   lsp_last_error().
+   Races: every call on one GPU uses that GPU's one array.  Calls on the same
+   stream are ordered; calls that overlap on one GPU (other streams, other
+   host threads without ordering) race and corrupt each other's results.
+   Arguments, output and other errors as lsp_periodogram. */
+#define LSP_NOALLOC_SCRATCH_BYTES (96u * 1024u * 1024u)
+lsp_status lsp_periodogram_noalloc(const double *t, const float *x, int64_t Nt,
+                                   double f_min, double df, int64_t Nf, float *Pn,
+                                   void *stream);
+
 /* Approximate periodogram by extirpolation and FFT (Press & Rybicki 1989,
    the approach Section 1 cites beside the direct sums), for comparison with
    the direct path: x - mean is spread onto a periodic grid of N points

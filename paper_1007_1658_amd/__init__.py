@@ -77,6 +77,7 @@ _D = ctypes.c_double
 SIGNATURES = {
     "lsp_periodogram": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P]),
     "lsp_periodogram_ex": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P, ctypes.POINTER(lsp_options)]),
+    "lsp_periodogram_noalloc": (_I32, [_P, _P, _I64, _D, _D, _I64, _P, _P]),
     "lsp_periodogram_batched": (_I32, [_P, _P, _P, _I32, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "lsp_mc_maxpower": (_I32, [_P, _P, _I32, _P, _P, _P, _I32, ctypes.c_uint64, ctypes.c_uint64, _P, _P]),
     "lsp_window_features": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
@@ -221,6 +222,28 @@ def _ptr(a):
 def lsp_periodogram(t, x, f_min: float, df: float, Nf: int, Pn=None, stream=None):
     """Pn[k] = Pn(f_min + k df), k < Nf, for device t (float64) and x (float32)."""
     return lsp_periodogram_ex(t, x, f_min, df, Nf, Pn=Pn, stream=stream)
+
+
+# size of the fixed per-GPU scratch array of lsp_periodogram_noalloc (include/lsp.h)
+LSP_NOALLOC_SCRATCH_BYTES = 96 * 1024 * 1024
+
+
+def lsp_periodogram_noalloc(t, x, f_min: float, df: float, Nf: int, Pn, stream=None):
+    """lsp_periodogram on the library's fixed scratch array: no device memory is
+    allocated by the library (Pn, the output, is the caller's)."""
+    torch = _torch()
+    _dev_tensor(t, torch.float64, "t")
+    _dev_tensor(x, torch.float32, "x")
+    _dev_tensor(Pn, torch.float32, "Pn")
+    if t.ndim != 1 or x.shape != t.shape:
+        raise ValueError("t and x must be 1-D and of equal length")
+    if Pn.numel() < int(Nf):
+        raise ValueError("Pn is shorter than Nf")
+    with torch.cuda.device(t.device):
+        st = lib().lsp_periodogram_noalloc(_ptr(t), _ptr(x), t.numel(), float(f_min), float(df), int(Nf),
+                                           _ptr(Pn), _stream_ptr(stream))
+    _check(st, "lsp_periodogram_noalloc")
+    return Pn
 
 
 def lsp_multiharmonic(t, y, K: int, f_min: float, df: float, Nf: int, w=None, p=None, waves=0, splits=0,

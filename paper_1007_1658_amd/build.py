@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libmi355lsp.so")
-SOURCES = ["pgram_kernels.hip", "pgram_mfma.hip", "batch_kernels.hip", "mlp_kernels.hip", "microbench.hip", "probe_kernels.hip", "fast_kernels.hip", "fast_host.cpp", "lsp_host.cpp",
+SOURCES = ["pgram_kernels.hip", "pgram_mfma.hip", "batch_kernels.hip", "mlp_kernels.hip", "microbench.hip", "probe_kernels.hip", "fast_kernels.hip", "noalloc.hip", "fast_host.cpp", "lsp_host.cpp",
            "tuner.cpp", "surrogate.cpp"]
 ARCH = os.environ.get("LSP_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -184,6 +184,10 @@ hipError_t launch_probe_recur(const double *t, int64_t n, double t_ref, double f
 int probe_recur_max();
 
 // records a message for lsp_last_error() on this host thread (lsp_host.cpp)
+// device address and size of this GPU's fixed scratch array (noalloc.hip);
+// looked up once per device, with that device current
+hipError_t noalloc_scratch(int dev, void **ptr, size_t *bytes);
+
 void set_last_error(const char *msg);
 void set_last_error(const std::string &msg);
 

@@ -272,9 +272,12 @@ static void split_geometry(int64_t Nt, int splits, int64_t *chunk, int *eff)
 }
 
 // Runs prep + main (+ reduce) for one curve on `s`.  Caller holds no lock.
+// fixed_cap > 0: the workspace is this device's fixed scratch array instead of
+// the stream's grow-only buffer (nothing is allocated); the sample axis is then
+// split into no more chunks than the array holds sums for.
 static lsp_status run_single(const double *t, const float *x, int64_t Nt, double f_min, double df,
                              int64_t Nf, float *Pn, hipStream_t s, int phase, lsp_tile tile,
-                             const CurveStats **stats_out, bool allow_profile)
+                             const CurveStats **stats_out, bool allow_profile, size_t fixed_cap = 0)
 {
     std::lock_guard<std::mutex> lock(ctx().mu);
     int dev = 0;
@@ -310,17 +313,37 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
         g_last_error = "launch shape not built into the library";
         return LSP_ERR_UNSUPPORTED;
     }
+    const int n_mom = moment_blocks(Nt);
+    char *base = nullptr;
+    if (fixed_cap > 0) {
+        void *p = nullptr;
+        size_t cap = 0;
+        const hipError_t he = noalloc_scratch(dev, &p, &cap);
+        if (he != hipSuccess) return hip_fail(he, "hipGetSymbolAddress(scratch)");
+        cap = std::min(cap, fixed_cap);
+        const Layout L1 = layout(Nt, Nf, 1, n_mom);
+        if (L1.total > cap) {
+            g_last_error = "needs " + std::to_string(L1.total) + " bytes of scratch, the fixed array holds " +
+                           std::to_string(cap);
+            return LSP_ERR_INVALID_ARG;
+        }
+        const size_t per_split = sizeof(float) * 4 * (size_t)Nf;
+        const size_t fit = cap >= L1.part + kAlign ? (cap - L1.part - (kAlign - 1)) / per_split : 1;
+        if ((size_t)tile.splits > fit) tile.splits = (int)std::max<size_t>(1, fit);
+        base = (char *)p;
+    }
     int64_t chunk = 0;
     int eff = 1;
     split_geometry(Nt, tile.splits, &chunk, &eff);
     tile.splits = eff;
 
-    const int n_mom = moment_blocks(Nt);
     const Layout L = layout(Nt, Nf, tile.splits, n_mom);
-    StreamCtx &sc = stream_ctx(dev, s);
-    st = ensure(sc.ws, L.total, s);
-    if (st != LSP_OK) return st;
-    char *base = (char *)sc.ws.ptr;
+    if (!base) {
+        StreamCtx &sc = stream_ctx(dev, s);
+        st = ensure(sc.ws, L.total, s);
+        if (st != LSP_OK) return st;
+        base = (char *)sc.ws.ptr;
+    }
     Records rec;
     rec.th = (float *)(base + L.th);
     rec.tl = (float *)(base + L.tl);
@@ -944,6 +967,28 @@ lsp_status lsp_periodogram(const double *t, const float *x, int64_t Nt, double f
                            int64_t Nf, float *Pn, void *stream)
 {
     return lsp_periodogram_ex(t, x, Nt, f_min, df, Nf, Pn, stream, nullptr);
+}
+
+lsp_status lsp_periodogram_noalloc(const double *t, const float *x, int64_t Nt, double f_min, double df,
+                                   int64_t Nf, float *Pn, void *stream)
+{
+    g_last_error.clear();
+    if (!t || !x || !Pn || Nt < 2 || Nt > kMaxNt || Nf < 1 || Nf > kMaxNf || !finite_nonneg(f_min) ||
+        !finite_pos(df) || !std::isfinite(f_min + (double)(Nf - 1) * df)) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    // the smallest workspace (one chunk of samples) must fit the fixed array
+    const Layout L1 = layout(Nt, Nf, 1, moment_blocks(Nt));
+    if (L1.total > (size_t)LSP_NOALLOC_SCRATCH_BYTES) {
+        g_last_error = "needs " + std::to_string(L1.total) + " bytes of scratch, the fixed array holds " +
+                       std::to_string((size_t)LSP_NOALLOC_SCRATCH_BYTES);
+        return LSP_ERR_INVALID_ARG;
+    }
+    lsp_tile tile;
+    std::memset(&tile, 0, sizeof(tile));
+    return run_single(t, x, Nt, f_min, df, Nf, Pn, (hipStream_t)stream, LSP_PHASE_SPLIT, tile, nullptr, false,
+                      (size_t)LSP_NOALLOC_SCRATCH_BYTES);
 }
 
 lsp_status lsp_periodogram_batched(const double *t, const float *x, const int64_t *off, int32_t n_curves,
