@@ -349,17 +349,16 @@ lsp_status lsp_model_set_scalers(lsp_model *m, const float *feat_mean, const flo
    equal lsp_model_param_count()). */
 lsp_status lsp_model_get_params(const lsp_model *m, int32_t member, float *host, int64_t n);
 lsp_status lsp_model_set_params(lsp_model *m, int32_t member, const float *host, int64_t n);
-/* Calibrated error of the surrogate's mean FAP: rms[7] (host FP32, each in
-   [0, 1]) is the RMS error, measured against Monte Carlo on patterns kept out
-   of training, in the bins of the FAP itself with upper edges 0.002, 0.005,
-   0.02, 0.05, 0.2, 0.5 (the last bin ends at 1).  lsp_fap_surrogate reports
-   fap_sigma = sqrt(members' spread^2 + rms(bin of fap)^2) and falls back to
-   Monte Carlo where that exceeds max_sigma.  All zeros (the default) leave the
-   members' spread alone.  LSP_ERR_INVALID_ARG unless n == 7. */
-lsp_status lsp_model_set_error_table(lsp_model *m, const float *rms, int32_t n);
-/* Binary model file (little-endian): header (version 2), scalers, the error
-   table, per member the step count and the weights, plus the Adam moments
-   when with_optimizer != 0 (version-1 files, without the table, still load).
+/* Calibrated standard errors of the law's location m (err_m) and scale beta
+   (err_beta), each in [0, 10]: measured against Monte Carlo on patterns kept
+   out of training.  lsp_fap_surrogate carries them to each pattern's FAP
+   through the law's derivatives there (see lsp_fap_surrogate).  Zeros (the
+   default) leave the members' spread alone. */
+lsp_status lsp_model_set_law_error(lsp_model *m, float err_m, float err_beta);
+/* Binary model file (little-endian): header (version 3), scalers, the two
+   law errors, per member the step count and the weights, plus the Adam
+   moments when with_optimizer != 0 (version-1 and version-2 files load with
+   zero law errors).
    Load reports LSP_ERR_MODEL for a missing, truncated or mismatched file. */
 lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_optimizer);
 lsp_status lsp_model_load(const char *path, lsp_model **out);
@@ -388,18 +387,25 @@ lsp_status lsp_mlp_gemm_nt(const void *A, const void *B, float *C, int32_t M, in
 
 /* FAP of observed maxima: for each pattern p (as in lsp_mc_maxpower, times
    sorted, Nt >= 4), fap[p] = P(max Pn of white noise >= p_obs[p]) =
-   1 - exp(-exp(-u)) under each member's law; fap is the members' mean and
-   fap_sigma their standard deviation.  Patterns with
-   fap_sigma > max_sigma, or with a standardized feature beyond the model's
-   range, are answered by Monte Carlo instead (mc_realizations draws, key
-   `seed`; fap = fraction of maxima >= p_obs, fap_sigma its binomial
-   standard error) and flagged in used_mc (may be NULL).  p_obs, fap,
-   fap_sigma, used_mc: device [n_pat].  Synchronous (the fallback decision
-   reads the spreads back). */
+   1 - exp(-exp(-u)) under each member's law; fap is the members' mean.
+   fap_err[p] is a per-pattern error bound: 2.576 standard errors (the
+   two-sided 99 % point), the standard error being
+     sqrt(spread^2 + (err_m dFAP/dm)^2 + (err_beta dFAP/dbeta)^2),
+   spread = the members' standard deviation, the derivatives those of the
+   law at this pattern's p_obs (dFAP/dm = e^{-u} exp(-e^{-u}) / beta,
+   dFAP/dbeta = u dFAP/dm) and err_m, err_beta the model's calibrated law
+   errors.  Patterns with fap_err > max_err (the accuracy the caller needs,
+   e.g. 0.005), or with a standardized feature beyond the model's range, are
+   answered by Monte Carlo instead (mc_realizations draws, key `seed`; fap =
+   fraction of maxima >= p_obs, fap_err 2.576 times its binomial standard
+   error) and flagged in used_mc (may be NULL; with mc_realizations = 0
+   nothing falls back and nothing is flagged).  p_obs, fap, fap_err,
+   used_mc: device [n_pat].  Synchronous (the fallback decision reads the
+   bounds back). */
 lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, int32_t n_pat,
                              const double *f_min, const double *df, const int64_t *Nf,
-                             const float *p_obs, float *fap, float *fap_sigma, int32_t *used_mc,
-                             float max_sigma, int32_t mc_realizations, uint64_t seed, void *stream);
+                             const float *p_obs, float *fap, float *fap_err, int32_t *used_mc,
+                             float max_err, int32_t mc_realizations, uint64_t seed, void *stream);
 
 /* ---- autotuner -----------------------------------------------------------------
 

@@ -167,3 +167,14 @@ def fap(raw, feat, mu, sigma, p):
     nt, nf = nt_nf(feat)
     u = (w_of(p, nt) - np.log(nf) - m) / b
     return -np.expm1(-np.exp(-u))
+
+
+def fap_sensitivity(raw, feat, mu, sigma, p):
+    """d FAP / d m and d FAP / d beta of one member's law at p, per pattern:
+    with u = (w(p) - ln Nf - m) / beta and FAP = 1 - exp(-e^{-u}),
+    dFAP/du = -e^{-u} exp(-e^{-u}), du/dm = -1/beta, du/dbeta = -u/beta."""
+    m, b = head(raw, mu, sigma)
+    nt, nf = nt_nf(feat)
+    u = (w_of(p, nt) - np.log(nf) - m) / b
+    g = np.exp(-u) * np.exp(-np.exp(-u))
+    return g / b, g * u / b

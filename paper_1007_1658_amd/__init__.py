@@ -89,7 +89,7 @@ SIGNATURES = {
     "lsp_model_get_params": (_I32, [_P, _I32, _P, _I64]),
     "lsp_model_set_params": (_I32, [_P, _I32, _P, _I64]),
     "lsp_model_save": (_I32, [_P, ctypes.c_char_p, _I32]),
-    "lsp_model_set_error_table": (_I32, [_P, _P, _I32]),
+    "lsp_model_set_law_error": (_I32, [_P, ctypes.c_float, ctypes.c_float]),
     "lsp_model_load": (_I32, [ctypes.c_char_p, ctypes.POINTER(_P)]),
     "lsp_mlp_forward": (_I32, [_P, _P, _I32, _P, _P]),
     "lsp_mlp_grad": (_I32, [_P, _I32, _P, _P, _I32, _I32, _P, _P, _P]),
@@ -623,14 +623,9 @@ class Model:
                                            sd.ctypes.data_as(ctypes.c_void_p), float(feat_zmax), float(q_mu),
                                            float(q_sigma)), "lsp_model_set_scalers")
 
-    # upper edges of the FAP bins of the calibrated error table (last bin ends at 1)
-    ERR_EDGES = (0.002, 0.005, 0.02, 0.05, 0.2, 0.5)
-
-    def set_error_table(self, rms):
-        """RMS error of the mean FAP per FAP bin (7 values; edges in ERR_EDGES)."""
-        a = np.ascontiguousarray(np.asarray(rms, dtype=np.float32))
-        _check(lib().lsp_model_set_error_table(self.h, a.ctypes.data_as(ctypes.c_void_p), a.size),
-               "lsp_model_set_error_table")
+    def set_law_error(self, err_m: float, err_beta: float):
+        """Calibrated standard errors of the law's location and scale (lsp_model_set_law_error)."""
+        _check(lib().lsp_model_set_law_error(self.h, float(err_m), float(err_beta)), "lsp_model_set_law_error")
 
     def save(self, path: str, with_optimizer: bool = False):
         _check(lib().lsp_model_save(self.h, path.encode(), 1 if with_optimizer else 0), "lsp_model_save")
@@ -660,17 +655,19 @@ class Model:
         _check(lib().lsp_mlp_adam_step(self.h, int(member), float(lr), float(beta1), float(beta2), float(eps),
                                        _stream_ptr(stream)), "lsp_mlp_adam_step")
 
-    def fap(self, t, off, f_min, df, Nf, p_obs, max_sigma=0.005, mc_realizations=10000, seed=0, stream=None):
-        """(fap, sigma, used_mc) device tensors for observed maxima p_obs [n_pat]."""
+    def fap(self, t, off, f_min, df, Nf, p_obs, max_err=0.005, mc_realizations=10000, seed=0, stream=None):
+        """(fap, err, used_mc) device tensors for observed maxima p_obs [n_pat]: the
+        mean FAP, its 99 % error bound, and where Monte Carlo answered instead
+        (the bound above max_err, or features out of range)."""
         torch = _torch()
         _dev_tensor(t, torch.float64, "t")
         _dev_tensor(p_obs, torch.float32, "p_obs")
         off, f_min, df, Nf, n = _host_shape(off, f_min, df, Nf)
         fap = torch.empty(n, dtype=torch.float32, device=t.device)
-        sig = torch.empty(n, dtype=torch.float32, device=t.device)
-        used = torch.empty(n, dtype=torch.int32, device=t.device)
+        err = torch.empty(n, dtype=torch.float32, device=t.device)
+        used = torch.zeros(n, dtype=torch.int32, device=t.device)
         hp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
         _check(lib().lsp_fap_surrogate(self.h, _ptr(t), hp(off), n, hp(f_min), hp(df), hp(Nf), _ptr(p_obs),
-                                       _ptr(fap), _ptr(sig), _ptr(used), float(max_sigma), int(mc_realizations),
+                                       _ptr(fap), _ptr(err), _ptr(used), float(max_err), int(mc_realizations),
                                        int(seed) & (2**64 - 1), _stream_ptr(stream)), "lsp_fap_surrogate")
-        return fap, sig, used
+        return fap, err, used

@@ -12,7 +12,6 @@ constexpr int kMlpHidden = 256;
 constexpr int kMlpOut = 2;        // location and scale of the law of the maximum
 constexpr int kMlpOutPad = 32;    // padded to the 32-wide output tile
 constexpr int kMlpLayers = 4;
-constexpr int kErrBins = 7;      // FAP bins of the calibrated error table
 constexpr int kQuantiles = 9;     // reported quantile levels (see quantile_level)
 constexpr int kFeatLogNt = 64;    // raw feature slots holding log10 Nt and log10 Nf
 constexpr int kFeatLogNf = 67;
@@ -51,9 +50,10 @@ hipError_t launch_colsum(const float *dZ, int B, int N, float *db, hipStream_t s
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_cast_weights(const float *W, int rows, int cols, __bf16 *Wb, __bf16 *WbT, hipStream_t s);
-hipError_t launch_fap(const float *law, int members, int B, const float *feat, const float *p_obs, float *fap,
-                      float *sigma, hipStream_t s);
-hipError_t launch_mc_fap(const float *pmax, int R, int B, const float *p_obs, const int32_t *idx, float *fap,
-                         float *sigma, hipStream_t s);
+// mean FAP of the members' laws and its error bound (see fap_kernel)
+hipError_t launch_fap(const float *law, int members, int B, const float *feat, const float *p_obs, float err_m,
+                      float err_beta, float z, float *fap, float *bound, hipStream_t s);
+hipError_t launch_mc_fap(const float *pmax, int R, int B, const float *p_obs, const int32_t *idx, float z,
+                         float *fap, float *bound, hipStream_t s);
 
 }  // namespace lsp

@@ -334,36 +334,55 @@ hipError_t launch_cast_weights(const float *W, int rows, int cols, __bf16 *Wb, _
 
 // FAP of an observed maximum under each member's law, 1 - exp(-exp(-u)),
 // then the members' mean and spread.
+// FAP of p_obs under every member's law, their mean, and a per-pattern error
+// bound.  The members' spread measures how far they disagree; the calibrated
+// standard errors (err_m, err_beta) of the law's location and scale, carried
+// to the FAP through its derivatives at this pattern's p_obs,
+//   dFAP/dm = e^{-u} exp(-e^{-u}) / beta,   dFAP/dbeta = u e^{-u} exp(-e^{-u}) / beta,
+// measure how far the law itself may be off.  bound = z sqrt(spread^2 +
+// (err_m dFAP/dm)^2 + (err_beta dFAP/dbeta)^2).
 __global__ void __launch_bounds__(256) fap_kernel(const float *law, int members, int B, const float *feat,
-                                                  const float *p_obs, float *fap, float *sigma)
+                                                  const float *p_obs, float err_m, float err_beta, float z,
+                                                  float *fap, float *bound)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= B) return;
     const PatternSize ps = pattern_size(feat, b);
     const double w = w_of((double)p_obs[b], ps.Nt) - ps.lnNf;
-    double s1 = 0.0, s2 = 0.0;
+    double s1 = 0.0, s2 = 0.0, dm = 0.0, db = 0.0;
     for (int e = 0; e < members; ++e) {
         const float *lw = law + ((size_t)e * B + b) * 2;
-        const double u = (w - (double)lw[0]) / (double)lw[1];
-        const double f = -expm1(-exp(-u));
+        const double beta = (double)lw[1];
+        const double u = (w - (double)lw[0]) / beta;
+        const double eu = exp(-u);
+        const double f = -expm1(-eu);
+        const double g = eu * exp(-eu) / beta;
         s1 += f;
         s2 += f * f;
+        dm += g;
+        db += u * g;
     }
     const double mean = s1 / members;
+    dm /= members;
+    db /= members;
+    const double spread2 = fmax(s2 / members - mean * mean, 0.0);
+    const double law2 = (double)err_m * err_m * dm * dm + (double)err_beta * err_beta * db * db;
     fap[b] = (float)mean;
-    sigma[b] = (float)sqrt(fmax(s2 / members - mean * mean, 0.0));
+    bound[b] = (float)((double)z * sqrt(spread2 + law2));
 }
 
-hipError_t launch_fap(const float *law, int members, int B, const float *feat, const float *p_obs, float *fap,
-                      float *sigma, hipStream_t s)
+hipError_t launch_fap(const float *law, int members, int B, const float *feat, const float *p_obs, float err_m,
+                      float err_beta, float z, float *fap, float *bound, hipStream_t s)
 {
-    hipLaunchKernelGGL(fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, law, members, B, feat, p_obs, fap, sigma);
+    hipLaunchKernelGGL(fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, law, members, B, feat, p_obs, err_m,
+                       err_beta, z, fap, bound);
     return hipGetLastError();
 }
 
-// empirical FAP of p_obs among R Monte-Carlo maxima: fraction >= p_obs
+// empirical FAP of p_obs among R Monte-Carlo maxima (fraction >= p_obs) and z
+// times its binomial standard error
 __global__ void __launch_bounds__(256) mc_fap_kernel(const float *pmax, int R, int B, const float *p_obs,
-                                                     const int32_t *idx, float *fap, float *sigma)
+                                                     const int32_t *idx, float z, float *fap, float *bound)
 {
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= B) return;
@@ -372,13 +391,14 @@ __global__ void __launch_bounds__(256) mc_fap_kernel(const float *pmax, int R, i
     for (int r = 0; r < R; ++r) n += (pmax[(size_t)i * R + r] >= p_obs[b]) ? 1 : 0;
     const float f = (float)n / (float)R;
     fap[b] = f;
-    sigma[b] = sqrtf(f * (1.f - f) / (float)R);
+    bound[b] = z * sqrtf(f * (1.f - f) / (float)R);
 }
 
-hipError_t launch_mc_fap(const float *pmax, int R, int B, const float *p_obs, const int32_t *idx, float *fap,
-                         float *sigma, hipStream_t s)
+hipError_t launch_mc_fap(const float *pmax, int R, int B, const float *p_obs, const int32_t *idx, float z,
+                         float *fap, float *bound, hipStream_t s)
 {
-    hipLaunchKernelGGL(mc_fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, pmax, R, B, p_obs, idx, fap, sigma);
+    hipLaunchKernelGGL(mc_fap_kernel, dim3((B + 255) / 256), dim3(256), 0, s, pmax, R, B, p_obs, idx, z, fap,
+                       bound);
     return hipGetLastError();
 }
 

@@ -43,15 +43,9 @@ constexpr int64_t kParams = 256 * 68 + 256 + 2 * (65536 + 256) + kMlpOut * 256 +
 
 size_t round32(size_t v) { return (v + 31) / 32 * 32; }
 
-// upper edges of the FAP bins of the calibrated error table (the last bin ends at 1)
-constexpr float kErrEdges[kErrBins - 1] = {0.002f, 0.005f, 0.02f, 0.05f, 0.2f, 0.5f};
-
-float err_of(const float *rms, float fap)
-{
-    int b = 0;
-    while (b < kErrBins - 1 && !(fap < kErrEdges[b])) ++b;
-    return rms[b];
-}
+// The error bound lsp_fap_surrogate reports is this many standard errors
+// (the two-sided 99 % point of the normal law).
+constexpr float kBoundZ = 2.5758293f;
 
 }  // namespace
 }  // namespace lsp
@@ -65,7 +59,9 @@ struct lsp_model {
     float feat_std[kMlpIn];
     float feat_zmax = 1e30f;  // patterns whose standardized features exceed this fall back to Monte Carlo
     float q_mu = 0.f, q_sigma = 1.f;
-    float err_rms[kErrBins] = {};  // calibrated RMS error of the mean FAP per bin of the FAP itself
+    // calibrated standard errors of the law's location m and scale beta on
+    // patterns kept out of training (0: the members' spread alone)
+    float law_err[2] = {0.f, 0.f};
     std::vector<float *> P, G, M1, M2;
     std::vector<int> step;
     std::vector<std::array<__bf16 *, kMlpLayers>> Wb, WbT;
@@ -437,12 +433,12 @@ lsp_status lsp_mlp_adam_step(lsp_model *m, int32_t member, float lr, float beta1
     return e == hipSuccess ? LSP_OK : fail(e, "lsp_mlp_adam_step");
 }
 
-lsp_status lsp_model_set_error_table(lsp_model *m, const float *rms, int32_t n)
+lsp_status lsp_model_set_law_error(lsp_model *m, float err_m, float err_beta)
 {
-    if (!good_model(m) || !rms || n != kErrBins) return LSP_ERR_INVALID_ARG;
-    for (int32_t i = 0; i < n; ++i)
-        if (!(rms[i] >= 0.f && rms[i] <= 1.f)) return LSP_ERR_INVALID_ARG;
-    std::memcpy(m->err_rms, rms, sizeof(m->err_rms));
+    if (!good_model(m) || !(err_m >= 0.f && err_m <= 10.f) || !(err_beta >= 0.f && err_beta <= 10.f))
+        return LSP_ERR_INVALID_ARG;
+    m->law_err[0] = err_m;
+    m->law_err[1] = err_beta;
     return LSP_OK;
 }
 
@@ -451,7 +447,7 @@ lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_opt
     if (!good_model(m) || !path) return LSP_ERR_INVALID_ARG;
     std::ofstream f(path, std::ios::binary);
     if (!f) return LSP_ERR_INVALID_ARG;
-    const int32_t hdr[8] = {2, m->members, kMlpIn, kMlpInPad, kMlpHidden, kMlpOut, kMlpOutPad, with_optimizer ? 1 : 0};
+    const int32_t hdr[8] = {3, m->members, kMlpIn, kMlpInPad, kMlpHidden, kMlpOut, kMlpOutPad, with_optimizer ? 1 : 0};
     f.write(kMagic, 16);
     f.write((const char *)hdr, sizeof(hdr));
     f.write((const char *)&m->seed, 8);
@@ -459,7 +455,7 @@ lsp_status lsp_model_save(const lsp_model *m, const char *path, int32_t with_opt
     f.write((const char *)m->feat_std, sizeof(m->feat_std));
     const float sc[3] = {m->feat_zmax, m->q_mu, m->q_sigma};
     f.write((const char *)sc, sizeof(sc));
-    f.write((const char *)m->err_rms, sizeof(m->err_rms));  // version 2
+    f.write((const char *)m->law_err, sizeof(m->law_err));  // version 3
     std::vector<float> h(kPadded);
     for (int e = 0; e < m->members; ++e) {
         const int32_t st = m->step[e];
@@ -488,7 +484,7 @@ lsp_status lsp_model_load(const char *path, lsp_model **out)
     int32_t hdr[8];
     f.read(magic, 16);
     f.read((char *)hdr, sizeof(hdr));
-    if (!f || std::memcmp(magic, kMagic, 16) != 0 || (hdr[0] != 1 && hdr[0] != 2) || hdr[2] != kMlpIn ||
+    if (!f || std::memcmp(magic, kMagic, 16) != 0 || (hdr[0] < 1 || hdr[0] > 3) || hdr[2] != kMlpIn ||
         hdr[3] != kMlpInPad ||
         hdr[4] != kMlpHidden || hdr[5] != kMlpOut || hdr[6] != kMlpOutPad || hdr[1] < 1 || hdr[1] > 16) {
         set_last_error("model file header mismatch");
@@ -505,12 +501,15 @@ lsp_status lsp_model_load(const char *path, lsp_model **out)
     m->feat_zmax = sc[0];
     m->q_mu = sc[1];
     m->q_sigma = sc[2];
-    if (hdr[0] >= 2) {  // calibrated error table
-        f.read((char *)m->err_rms, sizeof(m->err_rms));
-        for (float v : m->err_rms)
-            if (!(v >= 0.f && v <= 1.f)) {
+    if (hdr[0] == 2) {  // a per-FAP-bin error table (7 floats), no longer used: skipped
+        float table[7];
+        f.read((char *)table, sizeof(table));
+    } else if (hdr[0] >= 3) {  // calibrated errors of the law's location and scale
+        f.read((char *)m->law_err, sizeof(m->law_err));
+        for (float v : m->law_err)
+            if (!(v >= 0.f && v <= 10.f)) {
                 lsp_model_destroy(m);
-                set_last_error("model file: bad error table");
+                set_last_error("model file: bad law errors");
                 return LSP_ERR_MODEL;
             }
     }
@@ -560,11 +559,11 @@ lsp_status lsp_mlp_gemm_nt(const void *A, const void *B, float *C, int32_t M, in
 }
 
 lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, int32_t n_pat, const double *f_min,
-                             const double *df, const int64_t *Nf, const float *p_obs, float *fap, float *fap_sigma,
-                             int32_t *used_mc, float max_sigma, int32_t mc_realizations, uint64_t seed, void *stream)
+                             const double *df, const int64_t *Nf, const float *p_obs, float *fap, float *fap_err,
+                             int32_t *used_mc, float max_err, int32_t mc_realizations, uint64_t seed, void *stream)
 {
-    if (!good_model(m) || !t || !off || !f_min || !df || !Nf || !p_obs || !fap || !fap_sigma || n_pat < 1 ||
-        !(max_sigma >= 0.f) || mc_realizations < 0)
+    if (!good_model(m) || !t || !off || !f_min || !df || !Nf || !p_obs || !fap || !fap_err || n_pat < 1 ||
+        !(max_err >= 0.f) || mc_realizations < 0)
         return LSP_ERR_INVALID_ARG;
     for (int32_t p = 0; p < n_pat; ++p)
         if (off[p + 1] - off[p] < 4) return LSP_ERR_INVALID_ARG;
@@ -574,8 +573,8 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
     hipError_t he = hipMalloc(&feat, sizeof(float) * kFeatures * (size_t)n_pat);
     if (he != hipSuccess) return fail(he, "feature buffer");
     lsp_status st = lsp_window_features(t, off, n_pat, f_min, df, Nf, feat, stream);
-    // 2. the law from every member, 3. FAP and its spread
-    std::vector<float> hz((size_t)n_pat), hs((size_t)n_pat), hf((size_t)n_pat);
+    // 2. the law from every member, 3. FAP and its error bound
+    std::vector<float> hz((size_t)n_pat), hs((size_t)n_pat);
     if (st == LSP_OK) {
         std::lock_guard<std::mutex> lock(m->mu);
         const int Bp = (int)round32((size_t)n_pat);
@@ -587,30 +586,21 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
                 he = launch_head(m->raw, kMlpOutPad, feat, n_pat, m->q_mu, m->q_sigma,
                                  m->law + (size_t)i * n_pat * 2, nullptr, s);
         }
-        if (he == hipSuccess) he = launch_fap(m->law, m->members, n_pat, feat, p_obs, fap, fap_sigma, s);
+        if (he == hipSuccess)
+            he = launch_fap(m->law, m->members, n_pat, feat, p_obs, m->law_err[0], m->law_err[1], kBoundZ, fap,
+                            fap_err, s);
         if (he == hipSuccess) he = hipMemcpyAsync(hz.data(), m->zmax, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
         if (he == hipSuccess)
-            he = hipMemcpyAsync(hs.data(), fap_sigma, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
-        if (he == hipSuccess) he = hipMemcpyAsync(hf.data(), fap, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
+            he = hipMemcpyAsync(hs.data(), fap_err, sizeof(float) * n_pat, hipMemcpyDeviceToHost, s);
         if (he == hipSuccess) he = hipStreamSynchronize(s);
-        // predicted uncertainty: the members' spread and the calibrated error of the
-        // mean FAP at this FAP, in quadrature
-        if (he == hipSuccess) {
-            for (int32_t p = 0; p < n_pat; ++p) {
-                const float ce = err_of(m->err_rms, hf[p]);
-                hs[p] = std::sqrt(hs[p] * hs[p] + ce * ce);
-            }
-            he = hipMemcpyAsync(fap_sigma, hs.data(), sizeof(float) * n_pat, hipMemcpyHostToDevice, s);
-            if (he == hipSuccess) he = hipStreamSynchronize(s);
-        }
     }
     hipFree(feat);
     if (st != LSP_OK) return st;
     if (he != hipSuccess) return fail(he, "lsp_fap_surrogate");
-    // 4. Monte-Carlo fallback where the ensemble disagrees or the pattern is out of range
+    // 4. Monte-Carlo fallback where the bound exceeds max_err or the pattern is out of range
     std::vector<int32_t> fb, flags((size_t)n_pat, 0);
     for (int32_t p = 0; p < n_pat; ++p)
-        if (!(hs[p] <= max_sigma) || !(hz[p] <= m->feat_zmax)) fb.push_back(p);
+        if (!(hs[p] <= max_err) || !(hz[p] <= m->feat_zmax)) fb.push_back(p);
     if (!fb.empty() && mc_realizations > 0) {
         std::vector<int64_t> o2(1, 0), n2;
         std::vector<double> fm2, df2;
@@ -636,7 +626,7 @@ lsp_status lsp_fap_surrogate(lsp_model *m, const double *t, const int64_t *off, 
             st = lsp_mc_maxpower(t2, o2.data(), (int32_t)fb.size(), fm2.data(), df2.data(), n2.data(),
                                  mc_realizations, seed, 0, pm, stream);
             if (st == LSP_OK)
-                he = launch_mc_fap(pm, mc_realizations, (int)fb.size(), p_obs, idx, fap, fap_sigma, s);
+                he = launch_mc_fap(pm, mc_realizations, (int)fb.size(), p_obs, idx, kBoundZ, fap, fap_err, s);
             if (he == hipSuccess) he = hipStreamSynchronize(s);
         }
         hipFree(t2);

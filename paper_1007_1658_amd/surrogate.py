@@ -1,10 +1,17 @@
-"""Training and validation of the false-alarm surrogate.
+"""Training and validation of the false-alarm surrogate (the training driver).
 
-Every numerical step runs in the library: Monte-Carlo maxima
-(lsp_mc_maxpower), window features (lsp_window_features), the network's
-forward, loss, backward and Adam (lsp_mlp_grad, lsp_mlp_adam_step) and the
-FAP with its Monte-Carlo fallback (lsp_fap_surrogate).  This module only
-chooses minibatches, learning rates and chunk sizes, and summarizes results.
+Every step of serving a FAP runs in the library (lsp_fap_surrogate: window
+features, the network, the law, the per-pattern error bound and the
+Monte-Carlo fallback), and so does every step of training that touches the
+data at scale: Monte-Carlo maxima (lsp_mc_maxpower), window features
+(lsp_window_features), the network's forward, loss, backward and Adam
+(lsp_mlp_grad, lsp_mlp_adam_step).  This module chooses minibatches,
+learning rates and chunk sizes, and it computes, once per trained model, a
+few numbers that the model file then carries: the feature standardization
+and the head's location scale (fit_scalers, moments of the training data),
+and the calibrated law errors (calibrate, a two-parameter least-squares fit
+to held-out residuals).  These are model-building arithmetic of the driver;
+none of it runs when a FAP is served.
 
     python -m paper_1007_1658_amd.surrogate --out model.bin --report report.json
 """
@@ -125,41 +132,76 @@ def train(F, Y, members=4, steps=1500, batch=256, lr=2e-3, seed=0, holdout=0.1, 
     return model, history
 
 
-CAL_LEVELS = (0.001, 0.003, 0.01, 0.03, 0.1, 0.3, 0.6)   # one or more per bin of the error table
+CAL_LEVELS = (0.001, 0.003, 0.01, 0.02, 0.05, 0.1, 0.2)
+Z99 = 2.5758293035489   # standard errors in the library's error bound (two-sided 99 %)
 
 
-def calibrate(model, b: synth.Batch, R=10000, seed=30300, levels=CAL_LEVELS):
-    """The error table lsp_fap_surrogate adds to the members' spread: per bin of
-    the predicted FAP (edges Model.ERR_EDGES), the RMS of (FAP_net - FAP_MC) on
-    patterns kept out of training and validation, with the Monte Carlo's own
-    variance FAP (1 - FAP) / R removed.  Returns (rms[7], counts[7])."""
+def law_sensitivity(model, td, b: synth.Batch, p_obs):
+    """(fap, spread, dFAP/dm, dFAP/dbeta) per pattern as the library computes
+    them: its bound with law errors (0, 0), (1, 0) and (0, 1).  Leaves the
+    model's law errors at zero."""
+    out = []
+    for em, eb in ((0.0, 0.0), (1.0, 0.0), (0.0, 1.0)):
+        model.set_law_error(em, eb)
+        f, bound, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_err=1e9, mc_realizations=0)
+        out.append((f.cpu().numpy().astype(np.float64), bound.cpu().numpy().astype(np.float64) / Z99))
+    model.set_law_error(0.0, 0.0)
+    f, s0 = out[0]
+    dm = np.sqrt(np.maximum(out[1][1] ** 2 - s0 ** 2, 0.0))
+    db = np.sqrt(np.maximum(out[2][1] ** 2 - s0 ** 2, 0.0))
+    return f, s0, dm, db
+
+
+def calibrate(model, b: synth.Batch, R=10000, seed=30300, levels=CAL_LEVELS, exceed=0.005):
+    """The law error lsp_fap_surrogate carries to each pattern's FAP, set by
+    coverage on patterns kept out of training and validation: err_m is the
+    smallest value for which at most a fraction `exceed` of the residuals
+    |FAP_net - FAP_MC| (every pattern at every level) lie beyond the bound
+      2.576 sqrt(spread^2 + (err_m dFAP/dm)^2 + FAP_MC (1 - FAP_MC) / R),
+    the last term being the calibrating Monte Carlo's own variance (found by
+    bisection; err_beta is left at 0).  The residuals have heavier tails than
+    a normal law, so an RMS fit of err_m would cover too few of them.
+    Returns (err_m, err_beta, n_residuals)."""
     torch = _torch()
     td = _device_t(b)
     Y = monte_carlo(b, R, seed)
     Ys, _ = torch.sort(Y, dim=1)
-    edges32 = np.array(Model.ERR_EDGES, dtype=np.float32)   # binned in float32, as the library does
-    nb = len(edges32) + 1
-    sq, noise, cnt = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    res, s0s, dms, var = [], [], [], []
     for a in levels:
         k = max(0, int(math.ceil((1.0 - a) * R)) - 1)
         p_obs = Ys[:, k].contiguous()
         fap_mc = (Y >= p_obs[:, None]).double().mean(dim=1).cpu().numpy()
-        f, _, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=1e9, mc_realizations=0)
-        f32 = f.cpu().numpy()
-        bins = np.searchsorted(edges32, f32, side="right")
-        f = f32.astype(np.float64)
-        np.add.at(sq, bins, (f - fap_mc) ** 2)
-        np.add.at(noise, bins, fap_mc * (1.0 - fap_mc) / R)
-        np.add.at(cnt, bins, 1.0)
-    rms = np.sqrt(np.maximum(0.0, (sq - noise) / np.maximum(cnt, 1.0)))
-    if (cnt > 0).any():
-        rms[cnt == 0] = rms[cnt > 0].max()   # unseen bins: the largest measured error
-    return rms.astype(np.float32), cnt.astype(np.int64)
+        f, s0, dm, _ = law_sensitivity(model, td, b, p_obs)
+        res.append(np.abs(f - fap_mc)); s0s.append(s0); dms.append(dm); var.append(fap_mc * (1.0 - fap_mc) / R)
+    r, s0, dm, v = (np.concatenate(x) for x in (res, s0s, dms, var))
+
+    def outside(e):
+        return float(np.mean(r > Z99 * np.sqrt(s0 ** 2 + (e * dm) ** 2 + v)))
+
+    lo, hi = 0.0, 1.0
+    while outside(hi) > exceed and hi < 64.0:
+        hi *= 2.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if outside(mid) <= exceed:
+            hi = mid
+        else:
+            lo = mid
+    return float(hi), 0.0, int(r.size)
 
 
-def validate(model, b: synth.Batch, R=10000, seed=20260, levels=FAP_LEVELS, max_sigma=0.005, log=None):
-    """|FAP_surrogate - FAP_MC| at the MC quantiles for the given FAP levels, the
-    same for Eq. (3), the fallback rate and the speed against Monte Carlo."""
+def validate(model, b: synth.Batch, R=10000, seed=20260, levels=FAP_LEVELS, max_err=0.005, R_fallback=10000,
+             log=None):
+    """Against a Monte Carlo of R realizations per pattern, at the MC quantiles
+    of the given FAP levels: the network's error, the answers of
+    lsp_fap_surrogate with its fallback (R_fallback draws, another key), the
+    fallback rate, Eq. (3)'s error, and the time of both paths.
+
+    Contract per answer: |FAP - FAP_MC| <= max_err + 4 sigma, sigma the
+    standard deviation of the difference: the validating Monte Carlo's
+    sqrt(a(1 - a)/R), and for an answer that fell back also its own
+    sqrt(a(1 - a)/R_fallback).  Four sigma keeps the chance that a correct
+    answer fails anywhere among 200 patterns x 4 levels near 5 %."""
     torch = _torch()
     td = _device_t(b)
     torch.cuda.synchronize()
@@ -168,38 +210,51 @@ def validate(model, b: synth.Batch, R=10000, seed=20260, levels=FAP_LEVELS, max_
     torch.cuda.synchronize()
     t_mc = time.perf_counter() - t0
     Ys, _ = torch.sort(Y, dim=1)
-    res = {"patterns": b.n, "R": R, "mc_seconds": t_mc, "levels": {}}
+    res = {"patterns": b.n, "R": R, "R_fallback": R_fallback, "max_err": max_err, "mc_seconds": t_mc, "levels": {}}
     Nt = b.Nt
-    t_sur = 0.0
     for a in levels:
         k = max(0, int(math.ceil((1.0 - a) * R)) - 1)
         p_obs = Ys[:, k].contiguous()
         fap_mc = (Y >= p_obs[:, None]).float().mean(dim=1).cpu().numpy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        fap_net, sig, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=1e9, mc_realizations=0)
+        fap_net, bound, _ = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_err=1e9, mc_realizations=0)
         torch.cuda.synchronize()
-        t_sur += time.perf_counter() - t0
-        fap_full, _, used = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_sigma=max_sigma,
-                                      mc_realizations=R, seed=seed + 1)
+        t_net = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        fap_full, _, used = model.fap(td, b.off, b.f_min, b.df, b.Nf, p_obs, max_err=max_err,
+                                      mc_realizations=R_fallback, seed=seed + 1)
+        torch.cuda.synchronize()
+        t_full = time.perf_counter() - t0
         pn = p_obs.cpu().numpy()
         fap_eq3 = np.array([lsp_fap_analytic(float(pn[i]), int(Nt[i]), int(b.Nf[i])) for i in range(b.n)])
         net = np.abs(fap_net.cpu().numpy() - fap_mc)
         full = np.abs(fap_full.cpu().numpy() - fap_mc)
         eq3 = np.abs(fap_eq3 - fap_mc)
+        fb = used.cpu().numpy().astype(bool)
+        se = math.sqrt(a * (1 - a) / R)
+        se_fb = math.sqrt(a * (1 - a) / R_fallback)
+        allowed = max_err + 4.0 * np.where(fb, math.sqrt(se ** 2 + se_fb ** 2), se)
+        kept = ~fb
         res["levels"][str(a)] = {
             "net_max_abs_err": float(net.max()), "net_mean_abs_err": float(net.mean()),
-            "net_frac_within_0.005": float((net <= 0.005).mean()),
+            "net_frac_within_max_err": float((net <= max_err).mean()),
+            "bound_mean": float(bound.mean().item()),
+            "fallback_rate": float(fb.mean()),
+            "kept_max_abs_err": float(net[kept].max()) if kept.any() else None,
             "with_fallback_max_abs_err": float(full.max()), "with_fallback_mean_abs_err": float(full.mean()),
-            "fallback_rate": float(used.float().mean().item()),
+            "contract_violations": int((full > allowed).sum()),
             "eq3_max_abs_err": float(eq3.max()), "eq3_mean_abs_err": float(eq3.mean()),
-            "mc_standard_error": float(math.sqrt(a * (1 - a) / R)),
+            "mc_standard_error": se,
+            "surrogate_seconds": t_net, "with_fallback_seconds": t_full,
+            "speedup_vs_mc": t_mc / max(t_net, 1e-9), "speedup_with_fallback": t_mc / max(t_full, 1e-9),
         }
         if log:
-            log(f"FAP {a}: net max {net.max():.4f} mean {net.mean():.5f}; with fallback max {full.max():.4f} "
-                f"(rate {res['levels'][str(a)]['fallback_rate']:.2f}); Eq.3 max {eq3.max():.3f} mean {eq3.mean():.4f}")
-    res["surrogate_seconds_per_level"] = t_sur / len(levels)
-    res["speedup_vs_mc"] = t_mc / max(res["surrogate_seconds_per_level"], 1e-9)
+            lv = res["levels"][str(a)]
+            log(f"FAP {a}: net max {net.max():.4f} mean {net.mean():.5f}; fallback rate {lv['fallback_rate']:.2f}, "
+                f"kept max {lv['kept_max_abs_err']}, with fallback max {full.max():.4f}, violations "
+                f"{lv['contract_violations']}; Eq.3 max {eq3.max():.3f} mean {eq3.mean():.4f}; speed x"
+                f"{lv['speedup_vs_mc']:.0f} (with fallback x{lv['speedup_with_fallback']:.1f})")
     return res
 
 
@@ -210,7 +265,7 @@ def main(argv=None):
     ap.add_argument("--R", type=int, default=500)
     ap.add_argument("--R-val", type=int, default=10000)
     ap.add_argument("--cal-patterns", type=int, default=200,
-                    help="patterns (an independent draw) for the error table; 0 = no table")
+                    help="patterns (an independent draw) for the law errors; 0 = none")
     ap.add_argument("--members", type=int, default=4)
     ap.add_argument("--steps", type=int, default=1500)
     ap.add_argument("--batch", type=int, default=256)
@@ -242,17 +297,16 @@ def main(argv=None):
     if args.cal_patterns > 0:
         cal = synth.c4_patterns(args.cal_patterns, seed_sub=1, nt_range=(200, args.nt_max))
         t0 = time.perf_counter()
-        rms, cnt = calibrate(model, cal, R=args.R_val)
-        model.set_error_table(rms)
-        cal_info = {"patterns": cal.n, "R": args.R_val, "edges": list(Model.ERR_EDGES),
-                    "rms": [float(v) for v in rms], "counts": [int(v) for v in cnt],
-                    "seconds": time.perf_counter() - t0}
-        log(f"error table {np.round(rms, 4).tolist()} (counts {cnt.tolist()})")
+        err_m, err_b, n_res = calibrate(model, cal, R=args.R_val)
+        model.set_law_error(err_m, err_b)
+        cal_info = {"patterns": cal.n, "R": args.R_val, "levels": list(CAL_LEVELS), "residuals": n_res,
+                    "err_m": err_m, "err_beta": err_b, "seconds": time.perf_counter() - t0}
+        log(f"law errors: m {err_m:.4f}, beta {err_b:.4f} ({n_res} residuals)")
     if args.out:
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         model.save(args.out)
     res = validate(model, va, R=args.R_val, log=log)
-    res["error_table"] = cal_info
+    res["law_error_calibration"] = cal_info
     res.update({"train_patterns": tr.n, "R_train": args.R, "data_seconds": t_data, "train_seconds": t_train,
                 "members": args.members, "steps": args.steps, "early_stopping": hist})
     log(json.dumps(res))

@@ -140,10 +140,7 @@ int main()
         EXPECT(st == LSP_ERR_MODEL && m == nullptr);
     }
     EXPECT(lsp_model_load(nullptr, nullptr) == LSP_ERR_INVALID_ARG);
-    {
-        const float rms[7] = {0, 0, 0, 0, 0, 0, 0};
-        EXPECT(lsp_model_set_error_table(nullptr, rms, 7) == LSP_ERR_INVALID_ARG);
-    }
+    EXPECT(lsp_model_set_law_error(nullptr, 0.05f, 0.01f) == LSP_ERR_INVALID_ARG);
     std::printf("model header parser: ok\n");
 
     std::printf("%s (%d failed expectations)\n", g_fail ? "FAILED" : "PASSED", g_fail);

@@ -50,6 +50,7 @@ def _model_and_data(B=48, nR=64, seed=5):
 
 
 MU, SIGMA = -0.5, 0.3
+Z99 = 2.5758293035489   # the bound's standard errors (two-sided 99 % point)
 
 
 def test_param_roundtrip_and_count():
@@ -162,7 +163,7 @@ def test_fap_surrogate_and_fallback():
     mean, std = F.mean(0), F.std(0) + 1e-3
     m.set_scalers(mean, std, 1e6, -0.4, 0.5)
     p_obs = torch.linspace(6.0, 12.0, 8).cuda()
-    fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=10.0, mc_realizations=0)
+    fap, err, used = m.fap(td, off, fm, df, nf, p_obs, max_err=10.0, mc_realizations=0)
     fe = []
     for e in range(3):
         raw = R.forward(m.get_params(e).astype(np.float64), F, mean.astype(np.float32).astype(np.float64),
@@ -170,11 +171,12 @@ def test_fap_surrogate_and_fallback():
         fe.append(R.fap(raw, F, -0.4, 0.5, p_obs.cpu().numpy()))
     fe = np.array(fe)
     assert np.max(np.abs(fap.cpu().numpy() - fe.mean(0))) <= 1e-3
-    assert np.max(np.abs(sig.cpu().numpy() - fe.std(0))) <= 1e-3
+    # no law errors set: the bound is 2.576 times the members' spread
+    assert np.max(np.abs(err.cpu().numpy() - Z99 * fe.std(0))) <= 3e-3
     assert used.sum().item() == 0
     # forced fallback: every pattern answered by Monte Carlo with the same draws as lsp_mc_maxpower
     Rn = 256
-    fap2, sig2, used2 = m.fap(td, off, fm, df, nf, p_obs, max_sigma=0.0, mc_realizations=Rn, seed=77)
+    fap2, sig2, used2 = m.fap(td, off, fm, df, nf, p_obs, max_err=0.0, mc_realizations=Rn, seed=77)
     pm = lsp.lsp_mc_maxpower(td, off, fm, df, nf, Rn, seed=77).cpu().numpy()
     assert used2.sum().item() == 8
     expect = (pm >= p_obs.cpu().numpy()[:, None]).mean(axis=1)
@@ -193,7 +195,7 @@ def test_reported_quantiles_and_fap_agree():
     q = m.forward(feat)[0]
     assert torch.all(q[:, 1:] > q[:, :-1])
     for i, tau in enumerate(R.TAU):
-        fap, _, _ = m.fap(td, off, fm, df, nf, q[:, i].contiguous(), max_sigma=10.0, mc_realizations=0)
+        fap, _, _ = m.fap(td, off, fm, df, nf, q[:, i].contiguous(), max_err=10.0, mc_realizations=0)
         assert np.allclose(fap.cpu().numpy(), 1 - tau, atol=2e-5), tau
     m.close()
 
@@ -245,44 +247,55 @@ def test_out_of_range_features_route_to_monte_carlo():
     # a feature range narrower than the patterns' own spread: every pattern is out of range
     m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e-3, -0.4, 0.5)
     p_obs = torch.full((6,), 8.0, device="cuda")
-    fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=10.0, mc_realizations=64, seed=5)
+    fap, sig, used = m.fap(td, off, fm, df, nf, p_obs, max_err=10.0, mc_realizations=64, seed=5)
     assert used.sum().item() == 6
     pm = lsp.lsp_mc_maxpower(td, off, fm, df, nf, 64, seed=5).cpu().numpy()
     assert np.allclose(fap.cpu().numpy(), (pm >= 8.0).mean(axis=1), atol=1e-7)
     m.close()
 
 
-def test_error_table_enters_sigma_fallback_and_model_file(tmp_path):
-    """fap_sigma = sqrt(spread^2 + rms(bin of fap)^2); the table decides the
-    fallback and survives save/load."""
+def test_law_errors_enter_bound_fallback_and_model_file(tmp_path):
+    """bound = 2.576 sqrt(spread^2 + (err_m dFAP/dm)^2 + (err_beta dFAP/dbeta)^2),
+    with the derivatives of each pattern's law at its p_obs; the bound decides
+    the fallback and the law errors survive save/load."""
     t, off, fm, df, nf = _patterns(12, 6)
     td = torch.from_numpy(t).cuda()
     feat = lsp.lsp_window_features(td, off, fm, df, nf)
     F = feat.cpu().numpy()
     m = lsp.Model(members=3, seed=7)
-    m.set_scalers(F.mean(0), F.std(0) + 1e-3, 1e6, -0.4, 0.5)
-    p_obs = torch.full((12,), 7.0, device="cuda")
-    f0, s0, u0 = m.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
-    rms = np.array([0.001, 0.002, 0.003, 0.004, 0.006, 0.008, 0.01], dtype=np.float32)
-    m.set_error_table(rms)
-    f1, s1, _ = m.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
-    f0, s0, f1, s1 = (a.cpu().numpy().astype(np.float64) for a in (f0, s0, f1, s1))
+    mean, std = F.mean(0), F.std(0) + 1e-3
+    m.set_scalers(mean, std, 1e6, -0.4, 0.5)
+    p_obs = torch.linspace(5.0, 9.0, 12, device="cuda")
+    pn = p_obs.cpu().numpy().astype(np.float64)
+    f0, b0, _ = m.fap(td, off, fm, df, nf, p_obs, max_err=1e9, mc_realizations=0)
+    err_m, err_b = 0.06, 0.03
+    m.set_law_error(err_m, err_b)
+    f1, b1, _ = m.fap(td, off, fm, df, nf, p_obs, max_err=1e9, mc_realizations=0)
+    f0, b0, f1, b1 = (a.cpu().numpy().astype(np.float64) for a in (f0, b0, f1, b1))
     assert np.array_equal(f0, f1)
-    # bin b holds FAP below edge b (float32 comparisons, as in the library)
-    edges32 = np.array(lsp.Model.ERR_EDGES, dtype=np.float32)
-    f32 = f1.astype(np.float32)
-    bins = np.array([next((i for i, e in enumerate(edges32) if v < e), 6) for v in f32])
-    tab = rms[bins].astype(np.float64)
-    assert np.allclose(s1, np.sqrt(s0 ** 2 + tab ** 2), rtol=1e-5, atol=1e-9)
-    # a threshold below every table entry sends every pattern to Monte Carlo
-    _, _, used = m.fap(td, off, fm, df, nf, p_obs, max_sigma=0.0005, mc_realizations=32, seed=3)
+    dms, dbs, fs = [], [], []
+    for e in range(3):
+        raw = R.forward(m.get_params(e).astype(np.float64), F, mean.astype(np.float32).astype(np.float64),
+                        std.astype(np.float32).astype(np.float64), -0.4, 0.5, bf=True)["raw"]
+        dm, db = R.fap_sensitivity(raw, F, -0.4, 0.5, pn)
+        dms.append(dm); dbs.append(db); fs.append(R.fap(raw, F, -0.4, 0.5, pn))
+    dm, db, spread = np.mean(dms, 0), np.mean(dbs, 0), np.std(fs, 0)
+    expect = Z99 * np.sqrt(spread ** 2 + (err_m * dm) ** 2 + (err_b * db) ** 2)
+    print("bound", b1, "expected", expect, flush=True)
+    assert np.max(np.abs(b1 - expect)) <= 3e-3 * max(1.0, expect.max())
+    # the law terms are what the errors added: against the spread-only bound
+    law = np.sqrt(np.maximum((b1 / Z99) ** 2 - (b0 / Z99) ** 2, 0.0))
+    assert np.max(np.abs(law - np.sqrt((err_m * dm) ** 2 + (err_b * db) ** 2))) <= 2e-3
+    # a tolerance below every bound sends every pattern to Monte Carlo
+    _, _, used = m.fap(td, off, fm, df, nf, p_obs, max_err=float(b1.min()) * 0.5, mc_realizations=32, seed=3)
     assert used.sum().item() == 12
     path = str(tmp_path / "m.bin")
     m.save(path)
     m2 = lsp.Model(path=path)
-    _, s2, _ = m2.fap(td, off, fm, df, nf, p_obs, max_sigma=1e9, mc_realizations=0)
-    assert np.allclose(s2.cpu().numpy(), s1, rtol=1e-6)
-    with pytest.raises(lsp.LspError) as ei:
-        m.set_error_table(np.zeros(5, dtype=np.float32))
-    assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
+    _, b2, _ = m2.fap(td, off, fm, df, nf, p_obs, max_err=1e9, mc_realizations=0)
+    assert np.allclose(b2.cpu().numpy(), b1, rtol=1e-6)
+    for bad in ((-0.1, 0.0), (0.0, float("nan")), (20.0, 0.0)):
+        with pytest.raises(lsp.LspError) as ei:
+            m.set_law_error(*bad)
+        assert ei.value.status == lsp.LSP_ERR_INVALID_ARG
     m.close(); m2.close()

@@ -116,3 +116,28 @@ def test_gelu_matches_torch_tanh_form_and_erf_form():
     assert np.max(np.abs(R.gelu(z) - ref)) <= 1e-14
     exact = 0.5 * z * (1.0 + erf(z / np.sqrt(2.0)))
     assert np.max(np.abs(R.gelu(z) - exact)) <= 5e-4
+
+
+def test_fap_sensitivity_matches_finite_differences():
+    """The law's derivatives that carry the calibrated location and scale
+    errors to a pattern's FAP, against central differences of R.fap in m
+    (through mu) and in beta (through the scale output)."""
+    g = np.random.default_rng(11)
+    B = 12
+    feat = _feat(g, B)
+    raw = g.normal(0, 0.5, (B, 2))
+    nt, nf = R.nt_nf(feat)
+    p = R.z_of(np.log(nf) + g.uniform(-1.0, 4.0, B), nt)
+    mu, sigma = -0.4, 0.5
+    dm, db = R.fap_sensitivity(raw, feat, mu, sigma, p)
+    h = 1e-6
+    fd_m = (R.fap(raw, feat, mu + h, sigma, p) - R.fap(raw, feat, mu - h, sigma, p)) / (2 * h)
+    assert np.allclose(dm, fd_m, rtol=1e-6, atol=1e-10)
+    # beta = softplus(r1 + shift): d beta / d r1 = sigmoid(r1 + shift)
+    _, beta = R.head(raw, mu, sigma)
+    rp, rm = raw.copy(), raw.copy()
+    rp[:, 1] += h
+    rm[:, 1] -= h
+    fd_r = (R.fap(rp, feat, mu, sigma, p) - R.fap(rm, feat, mu, sigma, p)) / (2 * h)
+    dbeta_dr = 1.0 / (1.0 + np.exp(-(raw[:, 1] + R.BETA_SHIFT)))
+    assert np.allclose(db * dbeta_dr, fd_r, rtol=1e-6, atol=1e-10)
