@@ -520,6 +520,24 @@ def main():
                              "traffic": traffic_from_profiles(kv_name, args.config)},
                 "max_rel_err": err_v, "meets_1e-4": bool(err_v <= REL_TOL)}
 
+    # latency of one small call (c0: Nt 1000, Nf 2000), host to host: the launch-
+    # bound end of the range, where the paper's GPUs also paid a fixed cost
+    c0_latency = None
+    if args.config == "c1" and not args.no_plain:
+        from paper_1007_1658_amd import synth
+        c0 = synth.c0()
+        t0d, x0d = torch.from_numpy(c0.t).cuda(), torch.from_numpy(c0.x).cuda()
+        P0 = torch.empty(c0.Nf, dtype=torch.float32, device="cuda")
+        lat = []
+        for i in range(60):
+            torch.cuda.synchronize()
+            h0 = time.perf_counter()
+            lsp.lsp_periodogram(t0d, x0d, c0.f_min, c0.df, c0.Nf, Pn=P0)
+            torch.cuda.synchronize()
+            if i >= 10:
+                lat.append((time.perf_counter() - h0) * 1e3)
+        c0_latency = step_stats(lat)
+
     mfma = "mfma" in k_name
     peak = PEAK_FP16_TFLOPS if mfma else PEAK_FP32_TFLOPS
     # the method's 13 FLOP per term over the kernel's time, against the peak of
@@ -566,6 +584,7 @@ def main():
         "valu_form": valu,
         "roofline": roof,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(curve, args.cpu_seconds),
+        "c0_call_latency_ms": c0_latency,
     }
     if args.config == "paper":
         # the paper's own timing of this shape (Table 2: 20.3 s on a Tesla C1060, FP32,
