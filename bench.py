@@ -397,7 +397,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="use the heuristic launch shape")
     ap.add_argument("--form", default="auto", choices=["auto", "valu"],
                     help="auto: the library's (tuned) choice, the matrix-core form on MI355X; "
-                         "valu: time the FP32-VALU form (recurrence, compensated sums) instead")
+                         "valu: time the FP32-VALU form (frequency recurrence) instead")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--batched-form", default="", choices=["", "mfma", "recur"],
@@ -451,11 +451,14 @@ def main():
         if args.save_tune:
             lsp.lsp_tune_cache_save(args.save_tune)
 
-    valu_kw = dict(trig="recur", m=14, unroll=2, sum="kahan", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
+    # the VALU form's fastest whole call on c1 in a sweep of the built recurrence
+    # shapes (M, unroll, summation, waves, splits): two-level FP32 sums, whose
+    # error on c1 matches the compensated ones (both ~2e-6 of the sampled max)
+    valu_kw = dict(trig="recur", m=14, unroll=2, sum="two", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
     if args.form == "valu":
-        # the FP32-VALU form as the timed line (frequency recurrence, compensated sums)
+        # the FP32-VALU form as the timed line (frequency recurrence)
         tile = {"trig": lsp.LSP_TRIG_RECUR, "m": 14, "waves": 4, "splits": valu_kw["splits"], "unroll": 2,
-                "sum": lsp.LSP_SUM_KAHAN}
+                "sum": lsp.LSP_SUM_TWO}
 
         def run_split():
             lsp.lsp_periodogram_ex(t, x, curve.f_min, curve.df, curve.Nf, Pn=Pn, **valu_kw)
@@ -492,7 +495,7 @@ def main():
         plain = {"value": terms / sec_p, "ms_per_step": sec_p * 1e3, "max_rel_err": err_plain,
                  "meets_1e-4": bool(err_plain <= REL_TOL)}
 
-    # the FP32-VALU form beside it (frequency recurrence, compensated sums; the
+    # the FP32-VALU form beside it (frequency recurrence, two-level sums; the
     # shape the sweeps found best on c1), priced against the FP32 vector peak
     valu = None
     if not args.no_plain and args.form != "valu":

@@ -468,12 +468,22 @@ lsp_status lsp_microbench(int32_t kind, int32_t waves_per_simd, int32_t iters,
    as the recurrence form (LSP_TRIG_RECUR) makes them: the hardware sine and
    cosine of the SPLIT phase of f0, one rotation by the per-sample step angle
    2 pi step_df t' (FP64, rounded to FP32), then the three-term recurrence.
-   The kernels use step_df = 64 df.  1 <= M <= 32; c, s: FP32 [n M]. */
+   The kernels use step_df = 64 df.  1 <= M <= 32; c, s: FP32 [n M].
+
+   lsp_probe_cmac: one wave of the matrix-core form's complex product,
+   P[a][b] = sum_j L[a][j] R[b][j] for a, b < 32 and j < K (Eq. (8)'s sums as
+   the products of the k = 64 a + b factorization), with the kernels' operand
+   splitting (each value v as hi = fp16(v) plus lo = fp16(v - hi)) and
+   accumulation (hi*hi + hi*lo + lo*hi per real product on FP16 matrix cores,
+   FP32 sums).  L, R: FP32 complex [32][K] as interleaved (re, im); P: FP32
+   complex [32][32].  The kernels scale operands so that |value| <= 2^14.5 and
+   the lo halves stay normal.  K a multiple of 16 in [16, 4096]. */
 lsp_status lsp_probe_sincos(const float *r, int64_t n, float *s, float *c, void *stream);
 lsp_status lsp_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int32_t phase,
                            float *phi, void *stream);
 lsp_status lsp_probe_recurrence(const double *t, int64_t n, double t_ref, double f0, double step_df,
                                 int32_t M, float *c, float *s, void *stream);
+lsp_status lsp_probe_cmac(const float *L, const float *R, int32_t K, float *P, void *stream);
 
 /* ---- profiling hook ------------------------------------------------------------
 

@@ -182,6 +182,7 @@ hipError_t launch_probe_phase(const double *t, const double *f, int64_t n, doubl
 hipError_t launch_probe_recur(const double *t, int64_t n, double t_ref, double f0, double step_df, int M, float *c,
                               float *s, hipStream_t st);
 int probe_recur_max();
+hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hipStream_t s);
 
 // records a message for lsp_last_error() on this host thread (lsp_host.cpp)
 // device address and size of this GPU's fixed scratch array (noalloc.hip);

@@ -352,7 +352,10 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     rec.rs = (float *)(base + L.rs);
     rec.wv = nullptr;
     CurveStats *stats = (CurveStats *)(base + L.stats);
-    hipError_t e = launch_prep(t, x, Nt, (double)kWave * df, phase, (Moments *)(base + L.moments), n_mom,
+    // the step rotation records serve the recurrence form only; the matrix-core
+    // kernel reads the split times and values alone
+    const double step_df = (tile.trig == LSP_TRIG_MFMA) ? 0.0 : (double)kWave * df;
+    hipError_t e = launch_prep(t, x, Nt, step_df, phase, (Moments *)(base + L.moments), n_mom,
                                stats, rec, s);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
 
@@ -1064,6 +1067,19 @@ lsp_status lsp_probe_sincos(const float *r, int64_t n, float *s, float *c, void 
     lsp_status st = probe_device();
     if (st != LSP_OK) return st;
     hipError_t e = launch_probe_sincos(r, n, s, c, (hipStream_t)stream);
+    return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
+}
+
+lsp_status lsp_probe_cmac(const float *L, const float *R, int32_t K, float *P, void *stream)
+{
+    g_last_error.clear();
+    if (!L || !R || !P || K < 16 || K > 4096 || K % 16 != 0) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    lsp_status st = probe_device();
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_probe_cmac(L, R, K, P, (hipStream_t)stream);
     return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
 }
 

@@ -123,9 +123,9 @@ __device__ __forceinline__ void write_record(const Records &rec, int64_t j, doub
         return;
     }
     const double tp = tj - s.t_ref;
-    float th, tl, rc, rs;
+    float th, tl, rc = 1.0f, rs = 0.0f;
     split_time(tp, th, tl);
-    step_rotation(step_df, tp, rc, rs);
+    if (step_df != 0.0) step_rotation(step_df, tp, rc, rs);  // 0: no kernel of the call reads the step
     rec.th[j] = th;
     rec.tl[j] = tl;
     rec.xv[j] = xv;

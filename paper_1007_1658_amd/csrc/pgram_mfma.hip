@@ -340,6 +340,47 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
         }
 }
 
+// Probe of the matrix-core complex product on caller-given operands: one wave
+// forms P[a][b] = sum_j L[a][j] R[b][j] (a, b < 32, j < 16 K-steps of 16 j each,
+// i.e. K = 16 ks) with the kernels' own operand splitting (COp: hi/lo halves,
+// the -im halves by sign flip) and accumulation (LSP_CMAC: three FP16 passes
+// per real product into FP32).  L, R: FP32 complex [32][K] as (re, im) pairs;
+// P: FP32 complex [32][32].
+__global__ void __launch_bounds__(64) probe_cmac_kernel(const float *__restrict__ L, const float *__restrict__ R,
+                                                        int K, float *__restrict__ P)
+{
+    const int lane = threadIdx.x;
+    const int half = lane >> 5;
+    const int row = lane & 31;
+    floatx16 accR = floatx16{}, accI = floatx16{};
+    for (int j0 = 0; j0 < K; j0 += 16) {
+        const int js = j0 + 8 * half;
+        COp A, B;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const float *la = L + 2 * ((int64_t)row * K + js + i);
+            const float *rb = R + 2 * ((int64_t)row * K + js + i);
+            A.set(i, la[0], la[1]);
+            B.set(i, rb[0], rb[1]);
+        }
+        A.finish();
+        LSP_CMAC(A, B.rh, B.rl, B.ih, B.il, accR, accI);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = 8 * (r / 4) + 4 * half + (r % 4);
+        float *o = P + 2 * (a * 32 + row);
+        o[0] = accR[r];
+        o[1] = accI[r];
+    }
+}
+
+hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hipStream_t s)
+{
+    hipLaunchKernelGGL(probe_cmac_kernel, dim3(1), dim3(64), 0, s, L, R, K, P);
+    return hipGetLastError();
+}
+
 // 4- or 8-wave workgroups (an 8-wave group shares each block's R operands among
 // twice as many waves); 256 VGPRs at most either way, two waves per SIMD
 __global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }

@@ -100,6 +100,15 @@ def test_validation_happens_before_any_gpu_work():
         lsp.LSP_ERR_UNSUPPORTED
 
 
+def test_probe_validation_on_host():
+    L = lsp.lib()
+    null = ctypes.c_void_p(0)
+    fake = ctypes.c_void_p(16)
+    for args in ((null, fake, 16, fake), (fake, fake, 8, fake), (fake, fake, 24, fake), (fake, fake, 8192, fake),
+                 (fake, fake, 16, null)):
+        assert L.lsp_probe_cmac(*args, null) == lsp.LSP_ERR_INVALID_ARG, args
+
+
 def test_generalized_periodogram_validation_on_host():
     L = lsp.lib()
     null = ctypes.c_void_p(0)

@@ -142,3 +142,33 @@ def test_recurrence_error_per_step():
     m = np.arange(M)
     assert np.all(rms <= (m + 1) * 4e-6)
     assert np.all(worst <= 0.05)                    # a wrong coefficient or sign gives O(1) errors
+
+
+@pytest.mark.parametrize("K,kind", [(16, "unit"), (64, "unit"), (2048, "unit"), (64, "scaled"), (256, "mixed")])
+def test_matrix_core_complex_product(K, kind):
+    """The matrix-core form's complex product, P = L R^T over K samples, on
+    the kernels' own operand splitting and FP16 hi/lo accumulation, against
+    complex128.  Per element the error must stay below 2^-20 of sum_j |L_j| |R_j|
+    (three passes leave ~2^-22 per product; FP32 accumulation adds ~K 2^-24
+    relative to the partial sums).  A wrong sign of the -Im operand, a
+    transposed operand or a dropped pass fails by orders of magnitude."""
+    g = np.random.default_rng([41, K, len(kind)])
+    ph_l = g.uniform(-0.5, 0.5, (32, K))
+    ph_r = g.uniform(-0.5, 0.5, (32, K))
+    if kind == "unit":            # |L|, |R| = 1
+        amp_l, amp_r = np.ones((32, K)), np.ones((32, K))
+    elif kind == "scaled":        # the kernels' scales: values up to 2^14, trig factors 2^14
+        amp_l = 2.0 ** 14 * g.uniform(0.0, 1.0, (32, K))
+        amp_r = np.full((32, K), 2.0 ** 14)
+    else:                         # magnitudes spread over six decades
+        amp_l = 10.0 ** g.uniform(-3, 3, (32, K))
+        amp_r = 10.0 ** g.uniform(-3, 3, (32, K))
+    Lh = (amp_l * np.exp(2j * np.pi * ph_l)).astype(np.complex64)
+    Rh = (amp_r * np.exp(2j * np.pi * ph_r)).astype(np.complex64)
+    P = lsp.lsp_probe_cmac(torch.from_numpy(Lh).cuda(), torch.from_numpy(Rh).cuda()).cpu().numpy()
+    L64, R64 = Lh.astype(np.complex128), Rh.astype(np.complex128)
+    ref = L64 @ R64.T
+    scale = np.abs(L64) @ np.abs(R64).T
+    err = np.abs(P.astype(np.complex128) - ref) / scale
+    print(f"cmac K={K} {kind}: max |dP| / sum|L||R| = {err.max():.3e} (2^{np.log2(err.max()):.1f})", flush=True)
+    assert err.max() <= 2.0 ** -20
