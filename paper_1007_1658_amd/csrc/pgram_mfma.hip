@@ -20,9 +20,16 @@
 // Phases are FP64 products reduced to revolutions (as the SPLIT mode).
 //
 // Work split: a workgroup of W waves owns a-rows [32 W blockIdx.x, +32 W) and
-// all b; wave w owns 32 a-rows (one 32 x 64 output tile per sum).  Per
-// block of 64 samples the workgroup writes the R operands once to LDS (shared
-// by its waves); each lane builds its own L operands in registers.
+// all b; wave w owns 32 a-rows (64 frequencies each).  Per block of 64
+// samples the workgroup writes the R operands once to LDS (shared by its
+// waves); each lane builds its own L operands in registers.
+//
+// Conjugate pairs (the plain periodogram, mfma_sums_pm): the four real
+// products Lr Rr, Li Ri, Lr Ri, Li Rr of a complex product, accumulated
+// apart, give L R and L conj(R) alike, i.e. the sums at F_a + beta and at
+// F_a - beta.  Centring F_a in its 64 frequencies and taking beta_b =
+// (b + 1/2) df for b < 32 then covers all of them with half the matrix work
+// and half the R operands of the plain product over b < 64 (mfma_sums).
 //
 // The same products give the generalized (floating-mean, weighted)
 // periodogram named in Section 6.3 (Zechmeister & Kuerster 2009): with
@@ -59,15 +66,8 @@ __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
     lo = (_Float16)(v - (float)hi);
 }
 
-// the same for a v that is not a product: lo = fp16(v * one - hi) with `one`
-// equal to 1 but opaque to the compiler (held in a register), which then emits
-// one mixed-precision multiply-add instead of a conversion and a subtraction
-__device__ __forceinline__ void split16_sum(float v, float one, _Float16 &hi, _Float16 &lo)
-{
-    hi = (_Float16)v;
-    lo = (_Float16)fmaf(v, one, -(float)hi);
-}
-
+// 1.0f in a register the compiler cannot see into (an operand of the split
+// sequences below, which take their inputs in registers)
 __device__ __forceinline__ float opaque_one()
 {
     float one = 1.0f;
@@ -76,12 +76,14 @@ __device__ __forceinline__ float opaque_one()
 }
 
 // g e^{2i theta} from c = cos theta, s = sin theta: cos 2theta = 2c^2 - 1 and
-// sin 2theta = 2cs, as one product, one fused multiply-add and one product
-__device__ __forceinline__ void double_angle(float c, float s, float g, float &c2g, float &s2g)
+// sin 2theta = 2cs.  Returns t = 2 g c and the real part t c - g (one product,
+// one fused multiply-add); the imaginary part is the product t s, which the
+// hi/lo split below forms itself.
+__device__ __forceinline__ float double_angle(float c, float g, float &c2g)
 {
     const float t = c * (2.0f * g);
     c2g = fmaf(t, c, -g);
-    s2g = t * s;
+    return t;
 }
 
 // Debug build (LSP_POISON_LDS): once a block's shared operands have been
@@ -113,19 +115,83 @@ __device__ __forceinline__ halfx8 neg8(halfx8 v)
     return __builtin_bit_cast(halfx8, __builtin_bit_cast(u32x4, v) ^ 0x80008000u);
 }
 
-// the complex operand v = (re, im) as hi/lo FP16 halves, plus -im for the real
-// part (filled by set() for each of the 8 samples, then finish())
+// Two complex products z_i = p_i (c_i + i s_i), i = 0, 1, as FP16 hi/lo
+// halves packed two to a register (element i in half i): hi = fp16(p c),
+// lo = fp16(p c - hi), each one mixed-precision FMA on the exact product, so
+// the product itself is never rounded to FP32.  Written out because the
+// compiler forms each hi twice otherwise (once packed, once as the residual's
+// operand).  The leading s_nop covers a transcendental result read at once,
+// the trailing one the two wait states that a matrix instruction needs before
+// it reads a register a vector instruction wrote: hazards the compiler does
+// not track through inline assembly.
+__device__ __forceinline__ void split_cprod2(float p0, float c0, float s0, float p1, float c1, float s1,
+                                             unsigned &rh, unsigned &rl, unsigned &ih, unsigned &il)
+{
+    asm("s_nop 0\n\t"
+        "v_fma_mixlo_f16 %0, %4, %5, 0\n\t"
+        "v_fma_mixlo_f16 %2, %4, %6, 0\n\t"
+        "v_fma_mixhi_f16 %0, %7, %8, 0\n\t"
+        "v_fma_mixhi_f16 %2, %7, %9, 0\n\t"
+        "v_fma_mixlo_f16 %1, %4, %5, -%0 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixlo_f16 %3, %4, %6, -%2 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %1, %7, %8, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %3, %7, %9, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+        "s_nop 1"
+        : "=&v"(rh), "=&v"(rl), "=&v"(ih), "=&v"(il)
+        : "v"(p0), "v"(c0), "v"(s0), "v"(p1), "v"(c1), "v"(s1));
+}
+
+// The same for (r_i + i t_i s_i): the real parts r_i given as FP32 values
+// (hi by one packed conversion, lo = fp16(r - hi)), the imaginary parts as
+// products.
+__device__ __forceinline__ void split_csum2(float r0, float r1, float t0, float s0, float t1, float s1, float one,
+                                            unsigned &rh, unsigned &rl, unsigned &ih, unsigned &il)
+{
+    asm("s_nop 0\n\t"
+        "v_cvt_pk_f16_f32 %0, %4, %5\n\t"
+        "v_fma_mixlo_f16 %2, %6, %7, 0\n\t"
+        "v_fma_mixhi_f16 %2, %8, %9, 0\n\t"
+        "v_fma_mixlo_f16 %1, %4, %10, -%0 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixlo_f16 %3, %6, %7, -%2 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %1, %5, %10, -%0 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %3, %8, %9, -%2 op_sel:[0,0,1] op_sel_hi:[0,0,1]\n\t"
+        "s_nop 1"
+        : "=&v"(rh), "=&v"(rl), "=&v"(ih), "=&v"(il)
+        : "v"(r0), "v"(r1), "v"(t0), "v"(s0), "v"(t1), "v"(s1), "v"(one));
+}
+
+__device__ __forceinline__ void put2(halfx8 &v, int k, unsigned d)
+{
+    u32x4 t = __builtin_bit_cast(u32x4, v);
+    t[k] = d;
+    v = __builtin_bit_cast(halfx8, t);
+}
+
+// the complex operand v = (re, im) of 8 samples as hi/lo FP16 halves, plus -im
+// for the real part (filled by set_cprod() / set_csum() for each pair of
+// samples, then finish())
 struct COp {
     halfx8 rh, rl, ih, il, nih, nil;
-    __device__ __forceinline__ void set(int i, float re, float im)
+    // samples 2k, 2k + 1: v = p (c + i s)
+    __device__ __forceinline__ void set_cprod(int k, float p0, float c0, float s0, float p1, float c1, float s1)
     {
-        _Float16 h, l;
-        split16(re, h, l);
-        rh[i] = h;
-        rl[i] = l;
-        split16(im, h, l);
-        ih[i] = h;
-        il[i] = l;
+        unsigned a, b, c, d;
+        split_cprod2(p0, c0, s0, p1, c1, s1, a, b, c, d);
+        put2(rh, k, a);
+        put2(rl, k, b);
+        put2(ih, k, c);
+        put2(il, k, d);
+    }
+    // samples 2k, 2k + 1: v = r + i t s
+    __device__ __forceinline__ void set_csum(int k, float r0, float r1, float t0, float s0, float t1, float s1,
+                                             float one)
+    {
+        unsigned a, b, c, d;
+        split_csum2(r0, r1, t0, s0, t1, s1, one, a, b, c, d);
+        put2(rh, k, a);
+        put2(rl, k, b);
+        put2(ih, k, c);
+        put2(il, k, d);
     }
     // -im from im, a sign flip of both halves of each 32-bit word
     __device__ __forceinline__ void finish()
@@ -133,18 +199,27 @@ struct COp {
         nih = neg8(ih);
         nil = neg8(il);
     }
-    // set() with re not a product (see split16_sum)
-    __device__ __forceinline__ void set_sum(int i, float re, float im, float one)
-    {
-        _Float16 h, l;
-        split16_sum(re, one, h, l);
-        rh[i] = h;
-        rl[i] = l;
-        split16(im, h, l);
-        ih[i] = h;
-        il[i] = l;
-    }
 };
+
+// R operands of 8 samples (times t[0..7], one b): R = 2^14 e^{2 pi i b df t'}
+// and R2 = 2^14 e^{4 pi i b df t'}, as hi/lo halves
+__device__ __forceinline__ void build_r8(double bdf, const double *t, float one, COp &R, COp &R2)
+{
+    const float scale = kTrigScale;
+#pragma unroll
+    for (int i = 0; i < 8; i += 2) {
+        float c[2], s[2], tt[2], c2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float ph = rev_reduce(bdf * t[i + u]);
+            c[u] = cos_rev(ph);
+            s[u] = sin_rev(ph);
+            tt[u] = double_angle(c[u], kTrigScale, c2[u]);
+        }
+        R.set_cprod(i / 2, scale, c[0], s[0], scale, c[1], s[1]);
+        R2.set_csum(i / 2, c2[0], c2[1], tt[0], s[0], tt[1], s[1], one);
+    }
+}
 
 #define LSP_MFMA(A, B, C) C = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, C, 0, 0, 0)
 
@@ -230,21 +305,16 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
             const int b = task / (kMB / 8);
             const int g = task % (kMB / 8);
             const double bdf = (double)b * a.df;
-            halfx8 v[R_KINDS];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float ph = rev_reduce(bdf * S.t[8 * g + i]);
-                const float c = cos_rev(ph), s = sin_rev(ph);
-                float c2, s2;
-                double_angle(c, s, kTrigScale, c2, s2);
-                _Float16 h, l;
-                split16(c * kTrigScale, h, l); v[RR_H][i] = h; v[RR_L][i] = l;
-                split16(s * kTrigScale, h, l); v[RI_H][i] = h; v[RI_L][i] = l;
-                split16_sum(c2, one, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
-                split16(s2, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
-            }
-#pragma unroll
-            for (int q = 0; q < R_KINDS; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
+            COp R, R2;
+            build_r8(bdf, &S.t[8 * g], one, R, R2);
+            *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
+            *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
+            *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
+            *reinterpret_cast<halfx8 *>(&S.R[RI_L][b][8 * g]) = R.il;
+            *reinterpret_cast<halfx8 *>(&S.R[R2R_H][b][8 * g]) = R2.rh;
+            *reinterpret_cast<halfx8 *>(&S.R[R2R_L][b][8 * g]) = R2.rl;
+            *reinterpret_cast<halfx8 *>(&S.R[R2I_H][b][8 * g]) = R2.ih;
+            *reinterpret_cast<halfx8 *>(&S.R[R2I_L][b][8 * g]) = R2.il;
         }
         __syncthreads();
 #pragma unroll
@@ -253,20 +323,18 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
             // this lane's L operands: a-row `row`, samples js .. js+7
             COp L, L2, LW;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const float ph = rev_reduce(Fa * S.t[js + i]);
-                const float c = cos_rev(ph), s = sin_rev(ph);
-                const float xv = S.x[js + i];
-                L.set(i, xv * c, xv * s);
-                float c2, s2;
-                if (GLS) {
-                    const float wv = S.w[js + i];
-                    LW.set(i, wv * c, wv * s);
-                    double_angle(c, s, wv, c2, s2);
-                } else {
-                    double_angle(c, s, kTrigScale, c2, s2);
+            for (int i = 0; i < 8; i += 2) {
+                float c[2], s[2], t[2], c2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    c[u] = cos_rev(ph);
+                    s[u] = sin_rev(ph);
+                    t[u] = double_angle(c[u], GLS ? S.w[js + i + u] : kTrigScale, c2[u]);
                 }
-                L2.set_sum(i, c2, s2, one);
+                L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
+                if (GLS) LW.set_cprod(i / 2, S.w[js + i], c[0], s[0], S.w[js + i + 1], c[1], s[1]);
+                L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
             }
             L.finish();
             L2.finish();
@@ -340,6 +408,151 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
         }
 }
 
+// The sums of Eq. (8) for the plain periodogram with half the matrix work of
+// mfma_sums: the four real products of each complex product are kept apart,
+//   A = sum Lr Rr, B = sum Li Ri, C = sum Lr Ri, D = sum Li Rr,
+// and give both L R (A - B, C + D) and L conj(R) (A + B, D - C), i.e. the
+// sums at F_a + beta_b and at F_a - beta_b.  With F_a = f_min + (64 a + 31.5) df
+// and beta_b = (b + 1/2) df, b < 32, the two cover k = 64 a + 32 + b and
+// k = 64 a + 31 - b: all 64 frequencies of the a-row from one 32-wide b
+// range.  Same for the double-angle product.  Eight accumulators of 16 (a
+// 32 x 32 tile each), as many as mfma_sums<2, false> holds for the same
+// frequencies, with 24 instead of 48 matrix instructions per K-step, half the
+// R operands and no negated operands.
+__device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
+{
+    __shared__ MfmaLds<1, false> S;
+    const int tid = threadIdx.x;
+    const float one = opaque_one();
+    const int nw = blockDim.x / kWave;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int half = lane >> 5;   // which 8 samples of a K-step this lane carries
+    const int row = lane & 31;    // A: the lane's a-row; B: the lane's b-column
+    const int split = blockIdx.y;
+    const int64_t jb = (int64_t)split * a.chunk;
+    const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
+
+    // chunk scale: 2^(14 - e) with max|value| < 2^e
+    float mx = 0.f;
+    for (int64_t j = jb + tid; j < je; j += blockDim.x) mx = fmaxf(mx, fabsf(a.rec.xv[j]));
+    mx = wave_max(mx);
+    if (lane == 0) S.red[0][wave] = mx;
+    __syncthreads();
+    mx = S.red[0][0];
+    for (int w = 1; w < nw; ++w) mx = fmaxf(mx, S.red[0][w]);
+    int ex = 0;
+    (void)frexpf(mx, &ex);
+    const float xscale = ldexpf(1.0f, 14 - ex);
+
+    const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
+    const double Fa = a.f_min + ((double)(a_row * 64) + 31.5) * a.df;
+
+    // [A, B, C, D] of L R, then of L2 R2
+    floatx16 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = floatx16{};
+
+    for (int64_t j0 = jb; j0 < je; j0 += kMB) {
+        __syncthreads();  // the previous block's LDS is consumed
+        lds_poison(S);
+        if (tid < kMB) {
+            const int64_t j = j0 + tid;
+            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0
+            S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
+            S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
+        }
+        __syncthreads();
+        // R operands: 32 b x 8 groups of 8 samples, beta_b = (b + 1/2) df
+        for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
+            const int b = task / (kMB / 8);
+            const int g = task % (kMB / 8);
+            COp R, R2;
+            build_r8(((double)b + 0.5) * a.df, &S.t[8 * g], one, R, R2);
+            *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
+            *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
+            *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
+            *reinterpret_cast<halfx8 *>(&S.R[RI_L][b][8 * g]) = R.il;
+            *reinterpret_cast<halfx8 *>(&S.R[R2R_H][b][8 * g]) = R2.rh;
+            *reinterpret_cast<halfx8 *>(&S.R[R2R_L][b][8 * g]) = R2.rl;
+            *reinterpret_cast<halfx8 *>(&S.R[R2I_H][b][8 * g]) = R2.ih;
+            *reinterpret_cast<halfx8 *>(&S.R[R2I_L][b][8 * g]) = R2.il;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kMB / 16; ++ks) {
+            const int js = 16 * ks + 8 * half;
+            COp L, L2;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                float c[2], s[2], t[2], c2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    c[u] = cos_rev(ph);
+                    s[u] = sin_rev(ph);
+                    t[u] = double_angle(c[u], kTrigScale, c2[u]);
+                }
+                L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
+                L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
+            }
+            const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][row][js]);
+            const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][row][js]);
+            const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[RI_H][row][js]);
+            const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[RI_L][row][js]);
+            const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&S.R[R2R_H][row][js]);
+            const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][row][js]);
+            const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][row][js]);
+            const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][row][js]);
+            // hi x hi, hi x lo, lo x hi for each real product
+            LSP_MFMA(L.rh, rrh, acc[0]); LSP_MFMA(L.ih, rih, acc[1]);
+            LSP_MFMA(L.rh, rih, acc[2]); LSP_MFMA(L.ih, rrh, acc[3]);
+            LSP_MFMA(L2.rh, qrh, acc[4]); LSP_MFMA(L2.ih, qih, acc[5]);
+            LSP_MFMA(L2.rh, qih, acc[6]); LSP_MFMA(L2.ih, qrh, acc[7]);
+            LSP_MFMA(L.rh, rrl, acc[0]); LSP_MFMA(L.ih, ril, acc[1]);
+            LSP_MFMA(L.rh, ril, acc[2]); LSP_MFMA(L.ih, rrl, acc[3]);
+            LSP_MFMA(L2.rh, qrl, acc[4]); LSP_MFMA(L2.ih, qil, acc[5]);
+            LSP_MFMA(L2.rh, qil, acc[6]); LSP_MFMA(L2.ih, qrl, acc[7]);
+            LSP_MFMA(L.rl, rrh, acc[0]); LSP_MFMA(L.il, rih, acc[1]);
+            LSP_MFMA(L.rl, rih, acc[2]); LSP_MFMA(L.il, rrh, acc[3]);
+            LSP_MFMA(L2.rl, qrh, acc[4]); LSP_MFMA(L2.il, qih, acc[5]);
+            LSP_MFMA(L2.rl, qih, acc[6]); LSP_MFMA(L2.il, qrh, acc[7]);
+        }
+    }
+
+    // FP32 chunk sums, scales removed; CC as in mfma_sums (pads of the last
+    // block add 1 each to the double-angle real part)
+    const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
+    const float uz = 1.0f / (kTrigScale * kTrigScale);
+    const int64_t len = je - jb;
+    const int64_t pad_block = (len + kMB - 1) / kMB * kMB - len;
+    const int64_t pad_tile = (len + kTile - 1) / kTile * kTile - len;
+    const float count = (float)(len - pad_block + 2 * pad_tile);
+    float *part = a.part + (int64_t)split * 4 * a.Nf;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+        const float A = acc[0][r], B = acc[1][r], C = acc[2][r], D = acc[3][r];
+        const float A2 = acc[4][r], B2 = acc[5][r], C2 = acc[6][r], D2 = acc[7][r];
+        const int64_t kp = ar * 64 + 32 + row;  // F_a + beta_b: L R
+        const int64_t km = ar * 64 + 31 - row;  // F_a - beta_b: L conj(R)
+        if (kp < a.Nf) {
+            float *p = part + kp;
+            p[0] = (A - B) * ux;
+            p[a.Nf] = (C + D) * ux;
+            p[2 * a.Nf] = 0.5f * (count + (A2 - B2) * uz);
+            p[3 * a.Nf] = 0.5f * (C2 + D2) * uz;
+        }
+        if (km < a.Nf) {
+            float *p = part + km;
+            p[0] = (A + B) * ux;
+            p[a.Nf] = (D - C) * ux;
+            p[2 * a.Nf] = 0.5f * (count + (A2 + B2) * uz);
+            p[3 * a.Nf] = 0.5f * (D2 - C2) * uz;
+        }
+    }
+}
+
 // Probe of the matrix-core complex product on caller-given operands: one wave
 // forms P[a][b] = sum_j L[a][j] R[b][j] (a, b < 32, j < 16 K-steps of 16 j each,
 // i.e. K = 16 ks) with the kernels' own operand splitting (COp: hi/lo halves,
@@ -352,16 +565,17 @@ __global__ void __launch_bounds__(64) probe_cmac_kernel(const float *__restrict_
     const int lane = threadIdx.x;
     const int half = lane >> 5;
     const int row = lane & 31;
+    const float one = opaque_one();
     floatx16 accR = floatx16{}, accI = floatx16{};
     for (int j0 = 0; j0 < K; j0 += 16) {
         const int js = j0 + 8 * half;
         COp A, B;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
+        for (int i = 0; i < 8; i += 2) {
             const float *la = L + 2 * ((int64_t)row * K + js + i);
             const float *rb = R + 2 * ((int64_t)row * K + js + i);
-            A.set(i, la[0], la[1]);
-            B.set(i, rb[0], rb[1]);
+            A.set_cprod(i / 2, one, la[0], la[1], one, la[2], la[3]);
+            B.set_cprod(i / 2, one, rb[0], rb[1], one, rb[2], rb[3]);
         }
         A.finish();
         LSP_CMAC(A, B.rh, B.rl, B.ih, B.il, accR, accI);
@@ -383,7 +597,7 @@ hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hi
 
 // 4- or 8-wave workgroups (an 8-wave group shares each block's R operands among
 // twice as many waves); 256 VGPRs at most either way, two waves per SIMD
-__global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums<2, false>(a); }
+__global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums_pm(a); }
 
 __global__ void __launch_bounds__(512, 1) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
 
@@ -483,21 +697,16 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 const int b = task / (kMB / 8);
                 const int g = task % (kMB / 8);
                 const double bdf = (double)b * cv.df;
-                halfx8 v[R_KINDS];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float ph = rev_reduce(bdf * S.t[8 * g + i]);
-                    const float c = cos_rev(ph), s = sin_rev(ph);
-                    float c2, s2;
-                    double_angle(c, s, kTrigScale, c2, s2);
-                    _Float16 h, l;
-                    split16(c * kTrigScale, h, l); v[RR_H][i] = h; v[RR_L][i] = l;
-                    split16(s * kTrigScale, h, l); v[RI_H][i] = h; v[RI_L][i] = l;
-                    split16_sum(c2, one, h, l); v[R2R_H][i] = h; v[R2R_L][i] = l;
-                    split16(s2, h, l); v[R2I_H][i] = h; v[R2I_L][i] = l;
-                }
-#pragma unroll
-                for (int q = 0; q < R_KINDS; ++q) *reinterpret_cast<halfx8 *>(&S.R[q][b][8 * g]) = v[q];
+                COp R, R2;
+                build_r8(bdf, &S.t[8 * g], one, R, R2);
+                *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
+                *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
+                *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
+                *reinterpret_cast<halfx8 *>(&S.R[RI_L][b][8 * g]) = R.il;
+                *reinterpret_cast<halfx8 *>(&S.R[R2R_H][b][8 * g]) = R2.rh;
+                *reinterpret_cast<halfx8 *>(&S.R[R2R_L][b][8 * g]) = R2.rl;
+                *reinterpret_cast<halfx8 *>(&S.R[R2I_H][b][8 * g]) = R2.ih;
+                *reinterpret_cast<halfx8 *>(&S.R[R2I_L][b][8 * g]) = R2.il;
             }
             __syncthreads();
 #pragma unroll
@@ -506,14 +715,17 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 const int js = 16 * ks + 8 * half;
                 COp L, L2;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const float ph = rev_reduce(Fa * S.t[js + i]);
-                    const float c = cos_rev(ph), s = sin_rev(ph);
-                    const float xv = S.x[js + i];
-                    L.set(i, xv * c, xv * s);
-                    float c2, s2;
-                    double_angle(c, s, kTrigScale, c2, s2);
-                    L2.set_sum(i, c2, s2, one);
+                for (int i = 0; i < 8; i += 2) {
+                    float c[2], s[2], t[2], c2[2];
+#pragma unroll
+                    for (int u = 0; u < 2; ++u) {
+                        const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                        c[u] = cos_rev(ph);
+                        s[u] = sin_rev(ph);
+                        t[u] = double_angle(c[u], kTrigScale, c2[u]);
+                    }
+                    L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
+                    L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
                 }
                 L.finish();
                 L2.finish();
@@ -767,7 +979,7 @@ struct MhStep {
                 constexpr int q = P::wslot(M);
                 COp LW;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) LW.set(i, wv[i] * er[i], wv[i] * ei[i]);
+                for (int i = 0; i < 8; i += 2) LW.set_cprod(i / 2, wv[i], er[i], ei[i], wv[i + 1], er[i + 1], ei[i + 1]);
                 LW.finish();
                 LSP_CMAC(LW, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
             }
@@ -775,7 +987,7 @@ struct MhStep {
                 constexpr int q = P::vslot(M);
                 COp LX;
 #pragma unroll
-                for (int i = 0; i < 8; ++i) LX.set(i, xv[i] * er[i], xv[i] * ei[i]);
+                for (int i = 0; i < 8; i += 2) LX.set_cprod(i / 2, xv[i], er[i], ei[i], xv[i + 1], er[i + 1], ei[i + 1]);
                 LX.finish();
                 LSP_CMAC(LX, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
             }
