@@ -31,9 +31,10 @@ FLOP_PER_TERM = 13
 PEAK_FP32_TFLOPS = 157.3    # MI355X FP32 vector peak (256 CU x 2.4 GHz)
 PEAK_FP16_TFLOPS = 2500.0   # MI355X dense FP16 matrix peak
 # what the matrix-core form issues per term (a secondary figure, not the
-# method's work): two complex products (XC + i XS and the double-angle sum),
-# each four real products in three FP16 hi/lo passes, 24 multiply-adds
-MFMA_ISSUED_FLOP_PER_TERM = 48
+# method's work): per (a-row, b-column, sample) two complex products (XC + i XS
+# and the double-angle sum), each four real products in three FP16 hi/lo
+# passes, 24 multiply-adds, which serve the two frequencies F_a +- beta_b
+MFMA_ISSUED_FLOP_PER_TERM = 24
 REL_TOL = 1e-4
 
 WORKLOADS = {
@@ -559,8 +560,7 @@ def main():
         "flop_per_term": FLOP_PER_TERM,
     }
     if mfma:
-        # what the matrix pipe issues: 48 FLOP per term (two complex products,
-        # four real products each, three FP16 hi/lo passes)
+        # what the matrix pipe issues per term (MFMA_ISSUED_FLOP_PER_TERM)
         issued = MFMA_ISSUED_FLOP_PER_TERM * terms / k_avg_s / 1e12
         roof["mfma_issued"] = {"flop_per_term": MFMA_ISSUED_FLOP_PER_TERM, "achieved": issued,
                                "frac": issued / PEAK_FP16_TFLOPS}

@@ -194,8 +194,11 @@ __global__ void __launch_bounds__(256) pgram_kernel(PgramArgs a)
     }
 }
 
+// pads: the neutral samples (t' = 0, x = 0) that the main kernel counted in
+// CC, pad_count(Nt) for the vector kernels (whose last chunk is padded to
+// whole tiles), 0 for the matrix-core kernel (whose pads add nothing)
 __global__ void __launch_bounds__(256) pgram_reduce_kernel(const float *__restrict__ part, int splits,
-                                                           int64_t Nf, int64_t Nt,
+                                                           int64_t Nf, int64_t Nt, int64_t pads,
                                                            const CurveStats *__restrict__ st,
                                                            float *__restrict__ Pn)
 {
@@ -203,7 +206,7 @@ __global__ void __launch_bounds__(256) pgram_reduce_kernel(const float *__restri
     if (k >= Nf) return;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
     sum_chunks<4, 8>(part, splits, Nf, k, v);
-    v[2] -= (double)pad_count(Nt);  // chunks are whole tiles except the last
+    v[2] -= (double)pads;
     Pn[k] = pn_from_sums(v[0], v[1], v[2], v[3], (double)Nt, st->inv_var);
 }
 
@@ -320,8 +323,9 @@ hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hip
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nb = (a.Nf + 255) / 256;
+    const int64_t pads = (tile.trig == TR_MFMA) ? 0 : pad_count(a.Nt);
     hipLaunchKernelGGL(pgram_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const float *)a.part,
-                       tile.splits, a.Nf, a.Nt, a.stats, a.Pn);
+                       tile.splits, a.Nf, a.Nt, pads, a.stats, a.Pn);
     return hipGetLastError();
 }
 

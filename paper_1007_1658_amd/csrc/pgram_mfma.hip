@@ -29,7 +29,7 @@
 // apart, give L R and L conj(R) alike, i.e. the sums at F_a + beta and at
 // F_a - beta.  Centring F_a in its 64 frequencies and taking beta_b =
 // (b + 1/2) df for b < 32 then covers all of them with half the matrix work
-// and half the R operands of the plain product over b < 64 (mfma_sums).
+// and half the R operands of the plain product over b < 64.
 //
 // The same products give the generalized (floating-mean, weighted)
 // periodogram named in Section 6.3 (Zechmeister & Kuerster 2009): with
@@ -55,7 +55,7 @@ template <int NB, bool GLS>
 struct MfmaLds {
     double t[kMB];
     float x[kMB];
-    float w[GLS ? kMB : 1];
+    float w[kMB];  // GLS: weights; plain: the double-angle scale, 0 for pads
     float red[2][kMfmaMaxWaves];
     alignas(16) _Float16 R[R_KINDS][32 * NB][kMRow];  // 16-B rows: whole-row b128 reads and writes
 };
@@ -234,16 +234,13 @@ __device__ __forceinline__ void build_r8(double bdf, const double *t, float one,
         LSP_MFMA(L.nil, BIH, ACCR); LSP_MFMA(L.il, BRH, ACCI);                 \
     } while (0)
 
-// NB: 32-wide b subtiles per wave (b range 32 NB, k = 32 NB a + b).
-// GLS = false: sums XC + i XS and sum e^{2i wt}; slots [XC, XS, CC, CS].
-// GLS = true:  sums YC + i YS, C + i S and sum w e^{2i wt};
-//              slots [C, S, YC, YS, Re/2, Im/2] (weights normalized to 1).
-template <int NB, bool GLS>
-__device__ __forceinline__ void mfma_sums(const PgramArgs &a)
+// The generalized periodogram's sums, b range 32 (k = 32 a + b): YC + i YS,
+// C + i S and sum w e^{2i wt}; slots [C, S, YC, YS, Re/2, Im/2] (weights
+// normalized to 1).  Six accumulators of 16.
+__device__ __forceinline__ void gls_sums(const PgramArgs &a)
 {
-    constexpr int BW = 32 * NB;
-    constexpr int NACC = GLS ? 6 : 4;
-    __shared__ MfmaLds<NB, GLS> S;
+    constexpr int NB = 1, BW = 32, NACC = 6;
+    __shared__ MfmaLds<NB, true> S;
     const int tid = threadIdx.x;
     const float one = opaque_one();
     const int nw = blockDim.x / kWave;  // waves in the workgroup (1 to 8)
@@ -255,14 +252,14 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
     const int64_t jb = (int64_t)split * a.chunk;
     const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
 
-    // chunk scales: 2^(14 - e) with max|value| < 2^e (values; GLS: also weights)
+    // chunk scales: 2^(14 - e) with max|value| < 2^e (values and weights)
     float mx = 0.f, mw = 0.f;
     for (int64_t j = jb + tid; j < je; j += blockDim.x) {
         mx = fmaxf(mx, fabsf(a.rec.xv[j]));
-        if (GLS) mw = fmaxf(mw, a.rec.wv[j]);
+        mw = fmaxf(mw, a.rec.wv[j]);
     }
     mx = wave_max(mx);
-    if (GLS) mw = wave_max(mw);
+    mw = wave_max(mw);
     if (lane == 0) {
         S.red[0][wave] = mx;
         S.red[1][wave] = mw;
@@ -294,10 +291,10 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
         lds_poison(S);
         if (tid < kMB) {
             const int64_t j = j0 + tid;
-            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0 (GLS: w = 0)
+            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0, w = 0
             S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
             S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
-            if (GLS) S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
+            S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
         }
         __syncthreads();
         // R operands: BW b x 4 groups of 8 samples
@@ -330,15 +327,15 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
                     const float ph = rev_reduce(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
-                    t[u] = double_angle(c[u], GLS ? S.w[js + i + u] : kTrigScale, c2[u]);
+                    t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
                 }
                 L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
-                if (GLS) LW.set_cprod(i / 2, S.w[js + i], c[0], s[0], S.w[js + i + 1], c[1], s[1]);
+                LW.set_cprod(i / 2, S.w[js + i], c[0], s[0], S.w[js + i + 1], c[1], s[1]);
                 L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
             }
             L.finish();
             L2.finish();
-            if (GLS) LW.finish();
+            LW.finish();
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 const int bcol = 32 * n + row;
@@ -350,48 +347,15 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
                 const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][bcol][js]);
                 const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][bcol][js]);
                 const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][bcol][js]);
-                if (GLS) {
-                    LSP_CMAC(LW, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
-                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][2], acc[n][3]);
-                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][4], acc[n][5]);
-                } else {
-                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
-                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][2], acc[n][3]);
-                }
+                LSP_CMAC(LW, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
+                LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][2], acc[n][3]);
+                LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][4], acc[n][5]);
             }
         }
     }
 
     const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
-    if (GLS) {
-        const float uw = ldexpf(1.0f, ew - 28);   // 1 / (wscale 2^14)
-#pragma unroll
-        for (int n = 0; n < NB; ++n)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-                const int64_t k = ar * BW + 32 * n + row;
-                if (k < a.Nf) {
-                    float *p = a.part + (int64_t)split * 6 * a.Nf + k;
-                    p[0] = acc[n][0][r] * uw;
-                    p[a.Nf] = acc[n][1][r] * uw;
-                    p[2 * a.Nf] = acc[n][2][r] * ux;
-                    p[3 * a.Nf] = acc[n][3][r] * ux;
-                    p[4 * a.Nf] = 0.5f * acc[n][4][r] * uw;
-                    p[5 * a.Nf] = 0.5f * acc[n][5][r] * uw;
-                }
-            }
-        return;
-    }
-    // FP32 chunk sums, scales removed.  The merge subtracts one per sample that
-    // pads the series to whole 64-sample tiles (what the other kernels' neutral
-    // samples add to CC); here the ragged end is padded to a whole block, whose
-    // pads add 1 to Re of the second product, so CC gets the difference.
-    const float uz = 1.0f / (kTrigScale * kTrigScale);
-    const int64_t len = je - jb;
-    const int64_t pad_block = (len + kMB - 1) / kMB * kMB - len;     // pads of the last LDS block
-    const int64_t pad_tile = (len + kTile - 1) / kTile * kTile - len;  // pads the merge subtracts
-    const float count = (float)(len - pad_block + 2 * pad_tile);
+    const float uw = ldexpf(1.0f, ew - 28);   // 1 / (wscale 2^14)
 #pragma unroll
     for (int n = 0; n < NB; ++n)
 #pragma unroll
@@ -399,26 +363,58 @@ __device__ __forceinline__ void mfma_sums(const PgramArgs &a)
             const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
             const int64_t k = ar * BW + 32 * n + row;
             if (k < a.Nf) {
-                float *p = a.part + (int64_t)split * 4 * a.Nf + k;
-                p[0] = acc[n][0][r] * ux;
-                p[a.Nf] = acc[n][1][r] * ux;
-                p[2 * a.Nf] = 0.5f * (count + acc[n][2][r] * uz);
-                p[3 * a.Nf] = 0.5f * acc[n][3][r] * uz;
+                float *p = a.part + (int64_t)split * 6 * a.Nf + k;
+                p[0] = acc[n][0][r] * uw;
+                p[a.Nf] = acc[n][1][r] * uw;
+                p[2 * a.Nf] = acc[n][2][r] * ux;
+                p[3 * a.Nf] = acc[n][3][r] * ux;
+                p[4 * a.Nf] = 0.5f * acc[n][4][r] * uw;
+                p[5 * a.Nf] = 0.5f * acc[n][5][r] * uw;
             }
         }
 }
 
-// The sums of Eq. (8) for the plain periodogram with half the matrix work of
-// mfma_sums: the four real products of each complex product are kept apart,
+// The conjugate-pair products of one K-step: acc[0..3] += A, B, C, D of L R
+// (A = sum Lr Rr, B = sum Li Ri, C = sum Lr Ri, D = sum Li Rr), acc[4..7] the
+// same of L2 R2, each real product as hi x hi + hi x lo + lo x hi; R operands
+// of b-column `row` from the LDS staging area
+template <int NBR>
+__device__ __forceinline__ void pm_products(const COp &L, const COp &L2, const _Float16 (&R)[R_KINDS][NBR][kMRow],
+                                            int row, int js, floatx16 (&acc)[8])
+{
+    const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&R[RR_H][row][js]);
+    const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&R[RR_L][row][js]);
+    const halfx8 rih = *reinterpret_cast<const halfx8 *>(&R[RI_H][row][js]);
+    const halfx8 ril = *reinterpret_cast<const halfx8 *>(&R[RI_L][row][js]);
+    const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&R[R2R_H][row][js]);
+    const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&R[R2R_L][row][js]);
+    const halfx8 qih = *reinterpret_cast<const halfx8 *>(&R[R2I_H][row][js]);
+    const halfx8 qil = *reinterpret_cast<const halfx8 *>(&R[R2I_L][row][js]);
+    LSP_MFMA(L.rh, rrh, acc[0]); LSP_MFMA(L.ih, rih, acc[1]);
+    LSP_MFMA(L.rh, rih, acc[2]); LSP_MFMA(L.ih, rrh, acc[3]);
+    LSP_MFMA(L2.rh, qrh, acc[4]); LSP_MFMA(L2.ih, qih, acc[5]);
+    LSP_MFMA(L2.rh, qih, acc[6]); LSP_MFMA(L2.ih, qrh, acc[7]);
+    LSP_MFMA(L.rh, rrl, acc[0]); LSP_MFMA(L.ih, ril, acc[1]);
+    LSP_MFMA(L.rh, ril, acc[2]); LSP_MFMA(L.ih, rrl, acc[3]);
+    LSP_MFMA(L2.rh, qrl, acc[4]); LSP_MFMA(L2.ih, qil, acc[5]);
+    LSP_MFMA(L2.rh, qil, acc[6]); LSP_MFMA(L2.ih, qrl, acc[7]);
+    LSP_MFMA(L.rl, rrh, acc[0]); LSP_MFMA(L.il, rih, acc[1]);
+    LSP_MFMA(L.rl, rih, acc[2]); LSP_MFMA(L.il, rrh, acc[3]);
+    LSP_MFMA(L2.rl, qrh, acc[4]); LSP_MFMA(L2.il, qih, acc[5]);
+    LSP_MFMA(L2.rl, qih, acc[6]); LSP_MFMA(L2.il, qrh, acc[7]);
+}
+
+// The sums of Eq. (8) for the plain periodogram.  The four real products of
+// each complex product are kept apart,
 //   A = sum Lr Rr, B = sum Li Ri, C = sum Lr Ri, D = sum Li Rr,
 // and give both L R (A - B, C + D) and L conj(R) (A + B, D - C), i.e. the
 // sums at F_a + beta_b and at F_a - beta_b.  With F_a = f_min + (64 a + 31.5) df
 // and beta_b = (b + 1/2) df, b < 32, the two cover k = 64 a + 32 + b and
 // k = 64 a + 31 - b: all 64 frequencies of the a-row from one 32-wide b
 // range.  Same for the double-angle product.  Eight accumulators of 16 (a
-// 32 x 32 tile each), as many as mfma_sums<2, false> holds for the same
-// frequencies, with 24 instead of 48 matrix instructions per K-step, half the
-// R operands and no negated operands.
+// 32 x 32 tile each), as many as a complex product over b < 64 holds for the
+// same frequencies, with 24 instead of 48 matrix instructions per K-step,
+// half the R operands and no negated operands.
 __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
 {
     __shared__ MfmaLds<1, false> S;
@@ -461,6 +457,7 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
             const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0
             S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
             S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
+            S.w[tid] = ok ? kTrigScale : 0.0f;  // pads: L2 = 0, nothing to subtract later
         }
         __syncthreads();
         // R operands: 32 b x 8 groups of 8 samples, beta_b = (b + 1/2) df
@@ -491,43 +488,20 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
                     const float ph = rev_reduce(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
-                    t[u] = double_angle(c[u], kTrigScale, c2[u]);
+                    t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
                 }
                 L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
                 L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
             }
-            const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][row][js]);
-            const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][row][js]);
-            const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[RI_H][row][js]);
-            const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[RI_L][row][js]);
-            const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&S.R[R2R_H][row][js]);
-            const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][row][js]);
-            const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][row][js]);
-            const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][row][js]);
-            // hi x hi, hi x lo, lo x hi for each real product
-            LSP_MFMA(L.rh, rrh, acc[0]); LSP_MFMA(L.ih, rih, acc[1]);
-            LSP_MFMA(L.rh, rih, acc[2]); LSP_MFMA(L.ih, rrh, acc[3]);
-            LSP_MFMA(L2.rh, qrh, acc[4]); LSP_MFMA(L2.ih, qih, acc[5]);
-            LSP_MFMA(L2.rh, qih, acc[6]); LSP_MFMA(L2.ih, qrh, acc[7]);
-            LSP_MFMA(L.rh, rrl, acc[0]); LSP_MFMA(L.ih, ril, acc[1]);
-            LSP_MFMA(L.rh, ril, acc[2]); LSP_MFMA(L.ih, rrl, acc[3]);
-            LSP_MFMA(L2.rh, qrl, acc[4]); LSP_MFMA(L2.ih, qil, acc[5]);
-            LSP_MFMA(L2.rh, qil, acc[6]); LSP_MFMA(L2.ih, qrl, acc[7]);
-            LSP_MFMA(L.rl, rrh, acc[0]); LSP_MFMA(L.il, rih, acc[1]);
-            LSP_MFMA(L.rl, rih, acc[2]); LSP_MFMA(L.il, rrh, acc[3]);
-            LSP_MFMA(L2.rl, qrh, acc[4]); LSP_MFMA(L2.il, qih, acc[5]);
-            LSP_MFMA(L2.rl, qih, acc[6]); LSP_MFMA(L2.il, qrh, acc[7]);
+            pm_products(L, L2, S.R, row, js, acc);
         }
     }
 
-    // FP32 chunk sums, scales removed; CC as in mfma_sums (pads of the last
-    // block add 1 each to the double-angle real part)
+    // FP32 chunk sums, scales removed (the pads of the last block add
+    // nothing, and the merge subtracts none for this kernel)
     const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
     const float uz = 1.0f / (kTrigScale * kTrigScale);
-    const int64_t len = je - jb;
-    const int64_t pad_block = (len + kMB - 1) / kMB * kMB - len;
-    const int64_t pad_tile = (len + kTile - 1) / kTile * kTile - len;
-    const float count = (float)(len - pad_block + 2 * pad_tile);
+    const float count = (float)(je - jb);
     float *part = a.part + (int64_t)split * 4 * a.Nf;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -599,7 +573,7 @@ hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hi
 // twice as many waves); 256 VGPRs at most either way, two waves per SIMD
 __global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums_pm(a); }
 
-__global__ void __launch_bounds__(512, 1) gls_mfma_kernel(PgramArgs a) { mfma_sums<1, true>(a); }
+__global__ void __launch_bounds__(512, 1) gls_mfma_kernel(PgramArgs a) { gls_sums(a); }
 
 // ---------------------------------------------------------------------------
 // Batched form: a persistent workgroup takes (curve, block of 4 x 32 a-rows =
@@ -676,12 +650,12 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
         const int tile = wave % tiles;
         const int kg = wave / tiles;   // the wave's share of the K-steps within its group
         const int64_t a0 = ((int64_t)item.fblock * nw + tile) * 32;
-        const double Fa = cv.f_min + (double)((a0 + row) * 64) * cv.df;
-        floatx16 acc[2][4];
+        // conjugate pairs as in mfma_sums_pm: F_a centred in the a-row's 64
+        // frequencies, beta_b = (b + 1/2) df for b < 32
+        const double Fa = cv.f_min + ((double)((a0 + row) * 64) + 31.5) * cv.df;
+        floatx16 acc[8];  // [A, B, C, D] of L R, then of L2 R2
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) acc[n][q] = floatx16{};
+        for (int q = 0; q < 8; ++q) acc[q] = floatx16{};
 
         for (int64_t j0 = 0; j0 < Nt; j0 += kMB) {
             __syncthreads();
@@ -691,12 +665,13 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 const bool ok = j < Nt;
                 S.t[tid] = ok ? (double)th[j] + (double)tl[j] : 0.0;
                 S.x[tid] = ok ? xr[j] * xscale : 0.0f;
+                S.w[tid] = ok ? kTrigScale : 0.0f;  // pads: L2 = 0
             }
             __syncthreads();
-            for (int task = tid; task < 64 * (kMB / 8); task += blockDim.x) {
+            for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
                 const int b = task / (kMB / 8);
                 const int g = task % (kMB / 8);
-                const double bdf = (double)b * cv.df;
+                const double bdf = ((double)b + 0.5) * cv.df;
                 COp R, R2;
                 build_r8(bdf, &S.t[8 * g], one, R, R2);
                 *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
@@ -722,73 +697,56 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                         const float ph = rev_reduce(Fa * S.t[js + i + u]);
                         c[u] = cos_rev(ph);
                         s[u] = sin_rev(ph);
-                        t[u] = double_angle(c[u], kTrigScale, c2[u]);
+                        t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
                     }
                     L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
                     L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
                 }
-                L.finish();
-                L2.finish();
-#pragma unroll
-                for (int n = 0; n < 2; ++n) {
-                    const int bcol = 32 * n + row;
-                    const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][bcol][js]);
-                    const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][bcol][js]);
-                    const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[RI_H][bcol][js]);
-                    const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[RI_L][bcol][js]);
-                    const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&S.R[R2R_H][bcol][js]);
-                    const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][bcol][js]);
-                    const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][bcol][js]);
-                    const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][bcol][js]);
-                    LSP_CMAC(L, rrh, rrl, rih, ril, acc[n][0], acc[n][1]);
-                    LSP_CMAC(L2, qrh, qrl, qih, qil, acc[n][2], acc[n][3]);
-                }
+                pm_products(L, L2, S.R, row, js, acc);
             }
         }
 
-        // group sums by a fixed tree through the R staging area: in each round
-        // the upper half of the group (two waves in all, 64 KB of the 72 KB)
-        // stores its sums and the lower half adds them
+        // group sums by a fixed tree through the LDS staging area: in each
+        // round the upper half of the group (two waves in all, 64 KB of the
+        // 72 KB) stores its sums and the lower half adds them
         float *ps = reinterpret_cast<float *>(&S.R[0][0][0]);
         for (int h = grp / 2; h >= 1; h /= 2) {
             __syncthreads();  // the R operands (first round) or the last round's sums are read
             if (kg >= h && kg < 2 * h) {
                 const int slot = (kg - h) * tiles + tile;
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int q = 0; q < 8; ++q)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) ps[(slot * 128 + n * 64 + q * 16 + r) * kWave + lane] = acc[n][q][r];
+                    for (int r = 0; r < 16; ++r) ps[(slot * 128 + q * 16 + r) * kWave + lane] = acc[q][r];
             }
             __syncthreads();
             if (kg < h) {
                 const int slot = kg * tiles + tile;
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int q = 0; q < 8; ++q)
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r) acc[n][q][r] += ps[(slot * 128 + n * 64 + q * 16 + r) * kWave + lane];
+                    for (int r = 0; r < 16; ++r) acc[q][r] += ps[(slot * 128 + q * 16 + r) * kWave + lane];
             }
         }
         if (kg > 0) continue;  // the group's first wave evaluates the tile
-        // whole-curve sums; the ragged end was padded with samples at t' = 0,
-        // x = 0, each adding 1 to Re of the double-angle sum
+        // whole-curve sums (the ragged end's pads add nothing)
         const double ux = ldexp(1.0, ex - 28);
         const double uz = 1.0 / ((double)kTrigScale * (double)kTrigScale);
-        const double pads = (double)((Nt + kMB - 1) / kMB * kMB - Nt);
         const double inv_var = a.stats[item.curve].inv_var;
         unsigned long long best = 0ull;
 #pragma unroll
         for (int n = 0; n < 2; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int64_t k = (a0 + 8 * (r / 4) + 4 * half + (r % 4)) * 64 + 32 * n + row;
+                // n = 0: F_a + beta_b (L R), n = 1: F_a - beta_b (L conj(R))
+                const int64_t ar = a0 + 8 * (r / 4) + 4 * half + (r % 4);
+                const int64_t k = n == 0 ? ar * 64 + 32 + row : ar * 64 + 31 - row;
                 if (k < cv.Nf) {
-                    const double XC = (double)acc[n][0][r] * ux, XS = (double)acc[n][1][r] * ux;
-                    const double CC = 0.5 * ((double)Nt + (double)acc[n][2][r] * uz - pads);
-                    const double CS = 0.5 * (double)acc[n][3][r] * uz;
+                    const float sg = n == 0 ? -1.0f : 1.0f;
+                    const double XC = (double)(acc[0][r] + sg * acc[1][r]) * ux;
+                    const double XS = (double)(n == 0 ? acc[2][r] + acc[3][r] : acc[3][r] - acc[2][r]) * ux;
+                    const double CC = 0.5 * ((double)Nt + (double)(acc[4][r] + sg * acc[5][r]) * uz);
+                    const double CS = 0.5 * (double)(n == 0 ? acc[6][r] + acc[7][r] : acc[7][r] - acc[6][r]) * uz;
                     const float P = mfma_batch_epilogue(XC, XS, CC, CS, (double)Nt, inv_var, a.epi_mode);
                     if (a.Pn) a.Pn[cv.pn_off + k] = P;
                     const unsigned long long key = ((unsigned long long)__float_as_uint(P) << 32) |

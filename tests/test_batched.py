@@ -58,18 +58,24 @@ def test_batched_matches_oracle_per_curve(small_batch):
     assert np.all(t_ns[:, 1] >= t_ns[:, 0])
 
 
-def test_batched_equals_single_curve_calls(small_batch):
+def test_batched_equals_single_curve_calls(small_batch, batched_form):
+    """The batched launch against single-curve calls of the same kernel form.
+    (Across forms the bins where SS is small differ by more: curve 10 here has
+    Nt = 3 and SS = 0.0106 at its last bin, where a relative error e of the
+    FP32 sums becomes about e N / SS in Pn.  The oracle comparison above
+    covers the forms' accuracy.)"""
     b = small_batch
     t, x = _dev(b)
     out = lsp.lsp_periodogram_batched(t, x, b.off, b.f_min, b.df, b.Nf, want_pn=True)
     Pn = out["Pn"].cpu().numpy()
     pn_off = np.concatenate([[0], np.cumsum(b.Nf)])
+    single = dict(trig="mfma", m=32) if batched_form == "mfma" else dict(trig="recur", m=8)
     for c in range(0, b.n, 5):
         cv = b.curve(c)
         tc = torch.from_numpy(np.ascontiguousarray(cv.t)).cuda()
         xc = torch.from_numpy(np.ascontiguousarray(cv.x)).cuda()
-        Ps = lsp.lsp_periodogram_ex(tc, xc, cv.f_min, cv.df, cv.Nf, trig="recur", m=8, waves=4,
-                                    splits=1).cpu().numpy()
+        Ps = lsp.lsp_periodogram_ex(tc, xc, cv.f_min, cv.df, cv.Nf, waves=4, splits=1,
+                                    **single).cpu().numpy()
         Pg = Pn[pn_off[c]:pn_off[c + 1]]
         assert np.max(np.abs(Ps - Pg)) <= 1e-5 * Ps.max()
 
