@@ -221,6 +221,41 @@ __device__ __forceinline__ void build_r8(double bdf, const double *t, float one,
     }
 }
 
+// The same for 4 samples, written straight to the LDS staging area (row b,
+// samples s0 .. s0+3 of each operand kind)
+template <int NBR>
+__device__ __forceinline__ void build_r4(double bdf, const double *t, float one, _Float16 (&R)[R_KINDS][NBR][kMRow],
+                                         int b, int s0)
+{
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    u32x2 v[R_KINDS];
+    const float scale = kTrigScale;
+#pragma unroll
+    for (int i = 0; i < 4; i += 2) {
+        float c[2], s[2], tt[2], c2[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float ph = rev_reduce(bdf * t[i + u]);
+            c[u] = cos_rev(ph);
+            s[u] = sin_rev(ph);
+            tt[u] = double_angle(c[u], kTrigScale, c2[u]);
+        }
+        unsigned p, q, r, w;
+        split_cprod2(scale, c[0], s[0], scale, c[1], s[1], p, q, r, w);
+        v[RR_H][i / 2] = p;
+        v[RR_L][i / 2] = q;
+        v[RI_H][i / 2] = r;
+        v[RI_L][i / 2] = w;
+        split_csum2(c2[0], c2[1], tt[0], s[0], tt[1], s[1], one, p, q, r, w);
+        v[R2R_H][i / 2] = p;
+        v[R2R_L][i / 2] = q;
+        v[R2I_H][i / 2] = r;
+        v[R2I_L][i / 2] = w;
+    }
+#pragma unroll
+    for (int k = 0; k < R_KINDS; ++k) *reinterpret_cast<u32x2 *>(&R[k][b][s0]) = v[k];
+}
+
 #define LSP_MFMA(A, B, C) C = __builtin_amdgcn_mfma_f32_32x32x16_f16(A, B, C, 0, 0, 0)
 
 // accR += Re(L R), accI += Im(L R), three FP16 passes each
@@ -449,31 +484,43 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = floatx16{};
 
+    // the next block's samples, loaded into registers one block ahead so that
+    // the global-memory latency overlaps the current block's products
+    float pth = 0.f, ptl = 0.f, pxv = 0.f;
+    bool pok = false;
+    if (tid < kMB) {
+        const int64_t j = jb + tid;
+        pok = j < je;
+        if (pok) {
+            pth = a.rec.th[j];
+            ptl = a.rec.tl[j];
+            pxv = a.rec.xv[j];
+        }
+    }
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();  // the previous block's LDS is consumed
         lds_poison(S);
         if (tid < kMB) {
-            const int64_t j = j0 + tid;
-            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0
-            S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
-            S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
-            S.w[tid] = ok ? kTrigScale : 0.0f;  // pads: L2 = 0, nothing to subtract later
+            // ragged end: neutral samples t' = 0, x = 0, and a double-angle
+            // scale of 0 so that they add nothing to CC
+            S.t[tid] = pok ? (double)pth + (double)ptl : 0.0;
+            S.x[tid] = pok ? pxv * xscale : 0.0f;
+            S.w[tid] = pok ? kTrigScale : 0.0f;
+            const int64_t j = j0 + kMB + tid;
+            pok = j < je;
+            if (pok) {
+                pth = a.rec.th[j];
+                ptl = a.rec.tl[j];
+                pxv = a.rec.xv[j];
+            }
         }
         __syncthreads();
-        // R operands: 32 b x 8 groups of 8 samples, beta_b = (b + 1/2) df
-        for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
-            const int b = task / (kMB / 8);
-            const int g = task % (kMB / 8);
-            COp R, R2;
-            build_r8(((double)b + 0.5) * a.df, &S.t[8 * g], one, R, R2);
-            *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
-            *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
-            *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
-            *reinterpret_cast<halfx8 *>(&S.R[RI_L][b][8 * g]) = R.il;
-            *reinterpret_cast<halfx8 *>(&S.R[R2R_H][b][8 * g]) = R2.rh;
-            *reinterpret_cast<halfx8 *>(&S.R[R2R_L][b][8 * g]) = R2.rl;
-            *reinterpret_cast<halfx8 *>(&S.R[R2I_H][b][8 * g]) = R2.ih;
-            *reinterpret_cast<halfx8 *>(&S.R[R2I_L][b][8 * g]) = R2.il;
+        // R operands: 32 b x 16 groups of 4 samples, beta_b = (b + 1/2) df,
+        // one task per thread of an 8-wave workgroup
+        for (int task = tid; task < 32 * (kMB / 4); task += blockDim.x) {
+            const int b = task / (kMB / 4);
+            const int g = task % (kMB / 4);
+            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], one, S.R, b, 4 * g);
         }
         __syncthreads();
 #pragma unroll
@@ -657,15 +704,31 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
 #pragma unroll
         for (int q = 0; q < 8; ++q) acc[q] = floatx16{};
 
+        // the next block's samples, loaded one block ahead (as in mfma_sums_pm)
+        float pth = 0.f, ptl = 0.f, pxv = 0.f;
+        bool pok = false;
+        if (tid < kMB) {
+            pok = tid < Nt;
+            if (pok) {
+                pth = th[tid];
+                ptl = tl[tid];
+                pxv = xr[tid];
+            }
+        }
         for (int64_t j0 = 0; j0 < Nt; j0 += kMB) {
             __syncthreads();
             lds_poison(S);
             if (tid < kMB) {
-                const int64_t j = j0 + tid;
-                const bool ok = j < Nt;
-                S.t[tid] = ok ? (double)th[j] + (double)tl[j] : 0.0;
-                S.x[tid] = ok ? xr[j] * xscale : 0.0f;
-                S.w[tid] = ok ? kTrigScale : 0.0f;  // pads: L2 = 0
+                S.t[tid] = pok ? (double)pth + (double)ptl : 0.0;
+                S.x[tid] = pok ? pxv * xscale : 0.0f;
+                S.w[tid] = pok ? kTrigScale : 0.0f;  // pads: L2 = 0
+                const int64_t j = j0 + kMB + tid;
+                pok = j < Nt;
+                if (pok) {
+                    pth = th[j];
+                    ptl = tl[j];
+                    pxv = xr[j];
+                }
             }
             __syncthreads();
             for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
