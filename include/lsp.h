@@ -202,8 +202,9 @@ lsp_status lsp_periodogram_fast(const double *t, const float *x, int64_t Nt, dou
    t  device FP64 [Nt], y device FP32 [Nt], w device FP32 [Nt] weights >= 0
    (e.g. 1/sigma^2) or NULL for equal weights; Nt >= 3; grid as above;
    p device FP32 [Nf] output, fully written.  waves: 0 (library's choice,
-   8), 1, 2, 4 or 8 per workgroup; splits: 0 (library's choice) or the number of
-   chunks of the sample axis.  All weights zero or a constant y give p = 0.
+   4), 1, 2, 4 or 8 per workgroup (up to 4: conjugate-pair products, one
+   wave per SIMD; 8: plain complex products, two per SIMD); splits: 0
+   (library's choice) or the number of chunks of the sample axis.  All weights zero or a constant y give p = 0.
    Asynchronous on stream.  Errors: LSP_ERR_INVALID_ARG as above. */
 lsp_status lsp_gls(const double *t, const float *y, const float *w, int64_t Nt,
                    double f_min, double df, int64_t Nf, float *p, int32_t waves,

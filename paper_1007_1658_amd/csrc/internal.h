@@ -142,7 +142,8 @@ hipError_t launch_prep_weighted(const double *t, const float *y, const float *w,
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 // the multi-harmonic periodogram with K = 2 (pgram_mfma.hip): part[splits][12][Nf]
 hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
-constexpr int kGlsFreqPerWave = 32 * 32;
+constexpr int kGlsFreqPerWave = 32 * 32;      // generalized periodogram, 8-wave workgroups
+constexpr int kGlsPmFreqPerWave = 32 * 64;    // the same on conjugate pairs (up to 4 waves)
 // FP64 recomputation of the bins the weighted merges listed (K = 1: generalized)
 hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s);
 

@@ -890,8 +890,14 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     DeviceInfo *di = nullptr;
     lsp_status st = device_info(&dev, &di);
     if (st != LSP_OK) return st;
-    if (waves == 0) waves = (K == 1) ? 8 : 4;  // GLS: 8 waves share each block's R operands
-    if (splits == 0) splits = heuristic_splits(Nt, Nf, kGlsFreqPerWave / kWave, di->cus, waves, 2);
+    if (waves == 0) waves = 4;
+    if (splits == 0) {
+        // GLS with up to 4 waves: conjugate pairs, one wave per SIMD, 64
+        // frequencies per a-row
+        const bool pm = K == 1 && waves <= 4;
+        splits = heuristic_splits(Nt, Nf, (pm ? kGlsPmFreqPerWave : kGlsFreqPerWave) / kWave, di->cus, waves,
+                                  pm ? 4 / waves : 2);
+    }
     int64_t chunk = 0;
     int eff = 1;
     split_geometry(Nt, splits, &chunk, &eff);

@@ -409,6 +409,18 @@ __device__ __forceinline__ void gls_sums(const PgramArgs &a)
         }
 }
 
+// acc A += sum Lr Rr, B += sum Li Ri, C += sum Lr Ri, D += sum Li Rr, each in
+// three FP16 passes (hi x hi, hi x lo, lo x hi)
+#define LSP_PMAC(L, RRH, RRL, RIH, RIL, A, B, C, D)                             \
+    do {                                                                       \
+        LSP_MFMA(L.rh, RRH, A); LSP_MFMA(L.ih, RIH, B);                        \
+        LSP_MFMA(L.rh, RIH, C); LSP_MFMA(L.ih, RRH, D);                        \
+        LSP_MFMA(L.rh, RRL, A); LSP_MFMA(L.ih, RIL, B);                        \
+        LSP_MFMA(L.rh, RIL, C); LSP_MFMA(L.ih, RRL, D);                        \
+        LSP_MFMA(L.rl, RRH, A); LSP_MFMA(L.il, RIH, B);                        \
+        LSP_MFMA(L.rl, RIH, C); LSP_MFMA(L.il, RRH, D);                        \
+    } while (0)
+
 // The conjugate-pair products of one K-step: acc[0..3] += A, B, C, D of L R
 // (A = sum Lr Rr, B = sum Li Ri, C = sum Lr Ri, D = sum Li Rr), acc[4..7] the
 // same of L2 R2, each real product as hi x hi + hi x lo + lo x hi; R operands
@@ -574,6 +586,130 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
     }
 }
 
+// The generalized periodogram's sums on conjugate pairs (as mfma_sums_pm):
+// LW R, L R and L2W R2 with L = x e^{i theta}, LW = w e^{i theta},
+// L2W = w e^{2 i theta}, each as its four real products, so that one 32-wide
+// b range gives the a-row's 64 frequencies F_a +- beta_b.  Twelve
+// accumulators of 16 need one wave per SIMD (workgroups of at most 4 waves).
+// Slots as gls_sums: [C, S, YC, YS, Re/2, Im/2] of sum w e^{2i wt}.
+__device__ __forceinline__ void gls_sums_pm(const PgramArgs &a)
+{
+    __shared__ MfmaLds<1, true> S;
+    const int tid = threadIdx.x;
+    const float one = opaque_one();
+    const int nw = blockDim.x / kWave;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int half = lane >> 5;
+    const int row = lane & 31;
+    const int split = blockIdx.y;
+    const int64_t jb = (int64_t)split * a.chunk;
+    const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
+
+    // chunk scales: 2^(14 - e) with max|value| < 2^e (values and weights)
+    float mx = 0.f, mw = 0.f;
+    for (int64_t j = jb + tid; j < je; j += blockDim.x) {
+        mx = fmaxf(mx, fabsf(a.rec.xv[j]));
+        mw = fmaxf(mw, a.rec.wv[j]);
+    }
+    mx = wave_max(mx);
+    mw = wave_max(mw);
+    if (lane == 0) {
+        S.red[0][wave] = mx;
+        S.red[1][wave] = mw;
+    }
+    __syncthreads();
+    mx = S.red[0][0];
+    mw = S.red[1][0];
+    for (int w = 1; w < nw; ++w) {
+        mx = fmaxf(mx, S.red[0][w]);
+        mw = fmaxf(mw, S.red[1][w]);
+    }
+    int ex = 0, ew = 0;
+    (void)frexpf(mx, &ex);
+    (void)frexpf(mw, &ew);
+    const float xscale = ldexpf(1.0f, 14 - ex);
+    const float wscale = ldexpf(1.0f, 14 - ew);
+
+    const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
+    const double Fa = a.f_min + ((double)(a_row * 64) + 31.5) * a.df;
+
+    floatx16 acc[12];  // [A, B, C, D] of LW R, of L R, of L2W R2
+#pragma unroll
+    for (int q = 0; q < 12; ++q) acc[q] = floatx16{};
+
+    for (int64_t j0 = jb; j0 < je; j0 += kMB) {
+        __syncthreads();  // the previous block's LDS is consumed
+        lds_poison(S);
+        if (tid < kMB) {
+            const int64_t j = j0 + tid;
+            const bool ok = j < je;  // ragged end: neutral samples t' = 0, x = 0, w = 0
+            S.t[tid] = ok ? (double)a.rec.th[j] + (double)a.rec.tl[j] : 0.0;
+            S.x[tid] = ok ? a.rec.xv[j] * xscale : 0.0f;
+            S.w[tid] = ok ? a.rec.wv[j] * wscale : 0.0f;
+        }
+        __syncthreads();
+        for (int task = tid; task < 32 * (kMB / 4); task += blockDim.x) {
+            const int b = task / (kMB / 4);
+            const int g = task % (kMB / 4);
+            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], one, S.R, b, 4 * g);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kMB / 16; ++ks) {
+            const int js = 16 * ks + 8 * half;
+            COp L, LW, L2;
+#pragma unroll
+            for (int i = 0; i < 8; i += 2) {
+                float c[2], s[2], t[2], c2[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    c[u] = cos_rev(ph);
+                    s[u] = sin_rev(ph);
+                    t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
+                }
+                L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
+                LW.set_cprod(i / 2, S.w[js + i], c[0], s[0], S.w[js + i + 1], c[1], s[1]);
+                L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
+            }
+            const halfx8 rrh = *reinterpret_cast<const halfx8 *>(&S.R[RR_H][row][js]);
+            const halfx8 rrl = *reinterpret_cast<const halfx8 *>(&S.R[RR_L][row][js]);
+            const halfx8 rih = *reinterpret_cast<const halfx8 *>(&S.R[RI_H][row][js]);
+            const halfx8 ril = *reinterpret_cast<const halfx8 *>(&S.R[RI_L][row][js]);
+            LSP_PMAC(LW, rrh, rrl, rih, ril, acc[0], acc[1], acc[2], acc[3]);
+            LSP_PMAC(L, rrh, rrl, rih, ril, acc[4], acc[5], acc[6], acc[7]);
+            const halfx8 qrh = *reinterpret_cast<const halfx8 *>(&S.R[R2R_H][row][js]);
+            const halfx8 qrl = *reinterpret_cast<const halfx8 *>(&S.R[R2R_L][row][js]);
+            const halfx8 qih = *reinterpret_cast<const halfx8 *>(&S.R[R2I_H][row][js]);
+            const halfx8 qil = *reinterpret_cast<const halfx8 *>(&S.R[R2I_L][row][js]);
+            LSP_PMAC(L2, qrh, qrl, qih, qil, acc[8], acc[9], acc[10], acc[11]);
+        }
+    }
+
+    const float ux = ldexpf(1.0f, ex - 28);   // 1 / (xscale 2^14)
+    const float uw = ldexpf(1.0f, ew - 28);   // 1 / (wscale 2^14)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            // n = 0: F_a + beta_b (L R), n = 1: F_a - beta_b (L conj(R))
+            const int64_t k = n == 0 ? ar * 64 + 32 + row : ar * 64 + 31 - row;
+            if (k < a.Nf) {
+                const float sg = n == 0 ? -1.0f : 1.0f;
+                float *p = a.part + (int64_t)split * 6 * a.Nf + k;
+                p[0] = (acc[0][r] + sg * acc[1][r]) * uw;
+                p[a.Nf] = (n == 0 ? acc[2][r] + acc[3][r] : acc[3][r] - acc[2][r]) * uw;
+                p[2 * a.Nf] = (acc[4][r] + sg * acc[5][r]) * ux;
+                p[3 * a.Nf] = (n == 0 ? acc[6][r] + acc[7][r] : acc[7][r] - acc[6][r]) * ux;
+                p[4 * a.Nf] = 0.5f * (acc[8][r] + sg * acc[9][r]) * uw;
+                p[5 * a.Nf] = 0.5f * (n == 0 ? acc[10][r] + acc[11][r] : acc[11][r] - acc[10][r]) * uw;
+            }
+        }
+    }
+}
+
 // Probe of the matrix-core complex product on caller-given operands: one wave
 // forms P[a][b] = sum_j L[a][j] R[b][j] (a, b < 32, j < 16 K-steps of 16 j each,
 // i.e. K = 16 ks) with the kernels' own operand splitting (COp: hi/lo halves,
@@ -621,6 +757,8 @@ hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hi
 __global__ void __launch_bounds__(512, 1) pgram_mfma_kernel(PgramArgs a) { mfma_sums_pm(a); }
 
 __global__ void __launch_bounds__(512, 1) gls_mfma_kernel(PgramArgs a) { gls_sums(a); }
+// the conjugate-pair form: one wave per SIMD (at most 4 waves per workgroup)
+__global__ void __launch_bounds__(256, 1) gls_pm_kernel(PgramArgs a) { gls_sums_pm(a); }
 
 // ---------------------------------------------------------------------------
 // Batched form: a persistent workgroup takes (curve, block of 4 x 32 a-rows =
@@ -891,11 +1029,17 @@ __global__ void __launch_bounds__(256) gls_reduce_kernel(const float *__restrict
 
 hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const int64_t per_wave = 32 * 32;
+    // 8-wave workgroups: the plain complex products (32 frequencies per a-row);
+    // up to 4 waves: conjugate pairs (64 per a-row, one wave per SIMD)
+    const bool pm = waves <= 4;
+    const int64_t per_wave = pm ? kGlsPmFreqPerWave : kGlsFreqPerWave;
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + waves - 1) / waves;
     if (ev0) hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(gls_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
+    if (pm)
+        hipLaunchKernelGGL(gls_pm_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
+    else
+        hipLaunchKernelGGL(gls_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
     if (ev1) hipEventRecord(ev1, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
