@@ -63,7 +63,9 @@ GLS_FLOP_PER_TERM = 18
 def MH_FLOP_PER_TERM(K):
     return 24 * K - 1
 # what the matrix pipe issues per term: three complex products in three FP16
-# passes (36 multiply-adds) per harmonic
+# passes (36 multiply-adds) per harmonic; half that per term for the
+# generalized periodogram's conjugate-pair kernel, whose products serve two
+# frequencies each
 ISSUED_FLOP_PER_HARMONIC = 72
 
 
@@ -73,7 +75,8 @@ def make_curve(name):
 
 
 def kernel_source_hash(kernel_name=""):
-    name = "pgram_mfma.hip" if "mfma" in kernel_name else "pgram_kernels.hip"
+    in_mfma = "mfma" in kernel_name or kernel_name.startswith("gls_")
+    name = "pgram_mfma.hip" if in_mfma else "pgram_kernels.hip"
     p = os.path.join(ROOT, "paper_1007_1658_amd", "csrc", name)
     with open(p, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
@@ -341,7 +344,7 @@ def run_gls(args):
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     terms = c.Nt * c.Nf
     flop = MH_FLOP_PER_TERM(K) if mh else GLS_FLOP_PER_TERM
-    issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1)
+    issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1) // (2 if k_name == "gls_pm_kernel" else 1)
     achieved = flop * terms / k_avg_s / 1e12
     line = {
         "metric": (f"Nt·Nf terms/s of the multi-harmonic (K={K}) periodogram at max|Δp|≤1e-4" if mh else

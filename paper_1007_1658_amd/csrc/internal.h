@@ -58,6 +58,7 @@ struct PgramArgs {
     // ill-conditioned, listed by the merge for an FP64 recomputation
     uint32_t *refine_list;   // [Nf]
     uint32_t *refine_count;  // [1], zeroed by the weighted prep
+    double *refine_part;     // [kRefineBlocks][6 K + 2] partial FP64 sums of a bin split over workgroups
 };
 
 // Batched work item: one wave computes 64*m frequencies of one curve.
@@ -144,6 +145,10 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;      // generalized periodogram, 8-wave workgroups
 constexpr int kGlsPmFreqPerWave = 32 * 64;    // the same on conjugate pairs (up to 4 waves)
+// FP64 recomputation of listed bins: workgroups of the pass (a listed bin is
+// split over up to kRefineMaxParts of them when few bins are listed)
+constexpr int kRefineBlocks = 256;
+constexpr int kRefineMaxParts = 32;
 // FP64 recomputation of the bins the weighted merges listed (K = 1: generalized)
 hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s);
 

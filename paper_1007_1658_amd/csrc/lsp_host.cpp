@@ -372,6 +372,7 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     a.splits = tile.splits;
     a.refine_list = nullptr;
     a.refine_count = nullptr;
+    a.refine_part = nullptr;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (allow_profile && ctx().prof) {
@@ -919,6 +920,8 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     o = align_up(o + sizeof(uint32_t) * (size_t)Nf);
     const size_t o_count = o;
     o = align_up(o + sizeof(uint32_t));
+    const size_t o_rpart = o;  // partial FP64 sums of bins split over workgroups
+    o = align_up(o + sizeof(double) * (size_t)kRefineBlocks * (size_t)(6 * K + 2));
     StreamCtx &sc = stream_ctx(dev, s);
     st = ensure(sc.ws, o, s);
     if (st != LSP_OK) return st;
@@ -947,12 +950,13 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     a.splits = eff;
     a.refine_list = (uint32_t *)(base + o_list);
     a.refine_count = refine_count;
+    a.refine_part = (double *)(base + o_rpart);
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx().prof) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return hip_fail(hipGetLastError(), "hipEventCreate");
         ctx().prof_events.emplace_back(ev0, ev1);
-        ctx().prof_name = (K == 1) ? "gls_mfma_kernel" : "mh_mfma_kernel";
+        ctx().prof_name = (K == 1) ? (waves <= 4 ? "gls_pm_kernel" : "gls_mfma_kernel") : "mh_mfma_kernel";
     }
     e = (K == 1) ? launch_gls(a, waves, s, ev0, ev1) : launch_mh(a, K, waves, s, ev0, ev1);
     if (e != hipSuccess) return hip_fail(e, "generalized periodogram launch");

@@ -1005,10 +1005,12 @@ __device__ __forceinline__ double gls_power(double C, double Sn, double YC, doub
     if (!(YY > 0.0)) return 0.0;
     const double eps = fp64 ? 1e-12 : 1e-5;
     const bool two = fp64 ? (D > 1e-12) : (CC > eps && SS > eps && D > eps * eps);
-    if (two) return (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
-    if (CC > eps) return YC * YC / (YY * CC);
-    if (SS > eps) return YS * YS / (YY * SS);
-    return 0.0;
+    // a fraction of the variance, [0, 1] up to rounding, which is clipped
+    double p = 0.0;
+    if (two) p = (SS * YC * YC + CC * YS * YS - 2.0 * CS * YC * YS) / (YY * D);
+    else if (CC > eps) p = YC * YC / (YY * CC);
+    else if (SS > eps) p = YS * YS / (YY * SS);
+    return fmin(fmax(p, 0.0), 1.0);
 }
 
 // FP64 merge of the six chunk sums (slots C, S, YC, YS, C2/2, S2/2) and the
@@ -1359,7 +1361,9 @@ __device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64
         explained += z[i] * z[i];
     }
     *min_pivot = mp;
-    return (YY > 0.0) ? explained / YY : 0.0;
+    // a fraction of the variance: 1 at most (rounding in an interpolating fit,
+    // Nt = 2K + 1, can carry explained / YY past 1 by ~1e-5)
+    return (YY > 0.0) ? fmin(explained / YY, 1.0) : 0.0;
 }
 
 // FP64 merge of the 6K chunk sums and the least-squares solve; ill-conditioned
@@ -1382,12 +1386,15 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
     if (YY > 0.0 && !(piv >= kRefinePivot)) list[atomicAdd(count, 1u)] = (uint32_t)k;
 }
 
-// FP64 recomputation of the listed bins, one workgroup per bin: each thread
-// sums samples tid, tid + 256, ... from the records the matrix-core kernels
-// read (t' = th + tl, w/W, w (y - Y)/W), with the phase reduced and the sine
-// and cosine evaluated in FP64 and the harmonics by complex products; a
-// fixed-order tree adds the threads' sums (the value of a bin does not depend
-// on which workgroup takes it), then the solve runs with the FP64 rule.
+// FP64 recomputation of the listed bins: each thread sums samples tid,
+// tid + 256, ... from the records the matrix-core kernels read (t' = th + tl,
+// w/W, w (y - Y)/W), with the phase reduced and the sine and cosine evaluated
+// in FP64 and the harmonics by complex products; a fixed-order tree adds the
+// threads' sums, then the solve runs with the FP64 rule.  A bin takes one
+// workgroup, or, when few bins are listed (typically only f = 0), P of them
+// over consecutive sample ranges, whose sums a second kernel adds in range
+// order; P depends only on the number of listed bins, so a bin's value does
+// not depend on which workgroups take it.
 // The records hold the normalized weights and centred values rounded to FP32,
 // so their own totals W0 = sum w/W and Y0 = sum w (y - Y)/W (summed alongside,
 // in the same order) differ from 1 and 0 by rounding: every weight sum is
@@ -1395,6 +1402,34 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 // normal equations those of the records' own weights exactly (at f = 0 the
 // cosine sums then equal their weight total bit for bit, and the constant
 // direction is dropped as the oracle drops it).
+// workgroups per listed bin: the pass's kRefineBlocks workgroups spread over
+// the n listed bins, at most kRefineMaxParts each (1: a workgroup per bin,
+// which then also evaluates the power)
+__host__ __device__ __forceinline__ int refine_parts(uint32_t n)
+{
+    if (n == 0) return 1;
+    const uint32_t p = kRefineBlocks / n;
+    return p < 1 ? 1 : (p > (uint32_t)kRefineMaxParts ? kRefineMaxParts : (int)p);
+}
+
+// the FP64 power of one bin from its harmonic sums v[0 .. 6K) and the records'
+// weight and value totals v[6K], v[6K + 1] (normalized here)
+template <int K>
+__device__ __forceinline__ float refine_power(double *v, double YY)
+{
+    constexpr int NS = 6 * K;
+    const double W0 = v[NS], ybar = v[NS + 1] / W0;
+#pragma unroll
+    for (int q = 0; q < 4 * K; ++q) v[q] /= W0;
+#pragma unroll
+    for (int q = 0; q < 2 * K; ++q) v[4 * K + q] = v[4 * K + q] / W0 - ybar * v[q];
+    double d;
+    double p = 0.0;
+    if (W0 > 0.0)
+        p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d) : mh_power<K>(v, YY, true, &d);
+    return (float)p;
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
 {
@@ -1403,13 +1438,20 @@ __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
     __shared__ double red[NV][256];
     const int tid = threadIdx.x;
     const uint32_t n = *a.refine_count;
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const int P = refine_parts(n);
+    // P = 1: bins i = blockIdx.x, + gridDim.x, ...; P > 1: item q = blockIdx.x
+    // is part q % P of bin q / P (n P <= kRefineBlocks items)
+    const uint32_t items = (P == 1) ? n : n * (uint32_t)P;
+    for (uint32_t q = blockIdx.x; q < items; q += gridDim.x) {
+        const uint32_t i = q / (uint32_t)P;
+        const int part = (int)(q % (uint32_t)P);
         const int64_t k = (int64_t)a.refine_list[i];
         const double f = a.f_min + (double)k * a.df;
+        const int64_t jb = a.Nt * part / P, je = a.Nt * (part + 1) / P;
         double v[NV];
 #pragma unroll
-        for (int q = 0; q < NV; ++q) v[q] = 0.0;
-        for (int64_t j = tid; j < a.Nt; j += 256) {
+        for (int c = 0; c < NV; ++c) v[c] = 0.0;
+        for (int64_t j = jb + tid; j < je; j += 256) {
             const double tp = (double)a.rec.th[j] + (double)a.rec.tl[j];
             double ph = f * tp;
             ph -= rint(ph);
@@ -1435,45 +1477,70 @@ __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
             v[NS + 1] += y;
         }
 #pragma unroll
-        for (int q = 0; q < NV; ++q) red[q][tid] = v[q];
+        for (int c = 0; c < NV; ++c) red[c][tid] = v[c];
         __syncthreads();
         for (int w = 128; w > 0; w >>= 1) {
             if (tid < w) {
 #pragma unroll
-                for (int q = 0; q < NV; ++q) red[q][tid] += red[q][tid + w];
+                for (int c = 0; c < NV; ++c) red[c][tid] += red[c][tid + w];
             }
             __syncthreads();
         }
         if (tid == 0) {
+            if (P == 1) {
 #pragma unroll
-            for (int q = 0; q < NV; ++q) v[q] = red[q][0];
-            const double W0 = v[NS], ybar = v[NS + 1] / W0;
+                for (int c = 0; c < NV; ++c) v[c] = red[c][0];
+                a.Pn[k] = refine_power<K>(v, a.stats->var);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 4 * K; ++q) v[q] /= W0;
-#pragma unroll
-            for (int q = 0; q < 2 * K; ++q) v[4 * K + q] = v[4 * K + q] / W0 - ybar * v[q];
-            const double YY = a.stats->var;
-            double d;
-            double p = 0.0;
-            if (W0 > 0.0)
-                p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d)
-                             : mh_power<K>(v, YY, true, &d);
-            a.Pn[k] = (float)p;
+                for (int c = 0; c < NV; ++c) a.refine_part[(size_t)q * NV + c] = red[c][0];
+            }
         }
-        __syncthreads();  // red is reused by the next bin
+        __syncthreads();  // red is reused by the next item
     }
 }
 
-// the refinement pass: one workgroup per CU at most; workgroups past the
-// list's length (read on the device) exit at once
+// the bins split over workgroups: their parts added in order, then the power
+template <int K>
+__global__ void __launch_bounds__(256) mh_refine_finish_kernel(PgramArgs a)
+{
+    constexpr int NV = 6 * K + 2;
+    const uint32_t n = *a.refine_count;
+    const int P = refine_parts(n);
+    if (P == 1) return;
+    for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+        double v[NV];
+#pragma unroll
+        for (int c = 0; c < NV; ++c) v[c] = 0.0;
+        for (int part = 0; part < P; ++part)
+#pragma unroll
+            for (int c = 0; c < NV; ++c) v[c] += a.refine_part[((size_t)i * P + part) * NV + c];
+        a.Pn[a.refine_list[i]] = refine_power<K>(v, a.stats->var);
+    }
+}
+
+// the refinement pass: kRefineBlocks workgroups (fewer for a short grid);
+// items past the list's length (read on the device) are skipped at once
 hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s)
 {
-    const dim3 g((unsigned)(a.Nf < 256 ? a.Nf : 256)), b(256);
+    const dim3 g((unsigned)kRefineBlocks), b(256), g1(1);
     switch (K) {
-    case 1: hipLaunchKernelGGL(mh_refine_kernel<1>, g, b, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(mh_refine_kernel<2>, g, b, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(mh_refine_kernel<3>, g, b, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(mh_refine_kernel<4>, g, b, 0, s, a); break;
+    case 1:
+        hipLaunchKernelGGL(mh_refine_kernel<1>, g, b, 0, s, a);
+        hipLaunchKernelGGL(mh_refine_finish_kernel<1>, g1, b, 0, s, a);
+        break;
+    case 2:
+        hipLaunchKernelGGL(mh_refine_kernel<2>, g, b, 0, s, a);
+        hipLaunchKernelGGL(mh_refine_finish_kernel<2>, g1, b, 0, s, a);
+        break;
+    case 3:
+        hipLaunchKernelGGL(mh_refine_kernel<3>, g, b, 0, s, a);
+        hipLaunchKernelGGL(mh_refine_finish_kernel<3>, g1, b, 0, s, a);
+        break;
+    case 4:
+        hipLaunchKernelGGL(mh_refine_kernel<4>, g, b, 0, s, a);
+        hipLaunchKernelGGL(mh_refine_finish_kernel<4>, g1, b, 0, s, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
