@@ -478,13 +478,22 @@ lsp_status lsp_microbench(int32_t kind, int32_t waves_per_simd, int32_t iters,
    accumulation (hi*hi + hi*lo + lo*hi per real product on FP16 matrix cores,
    FP32 sums).  L, R: FP32 complex [32][K] as interleaved (re, im); P: FP32
    complex [32][32].  The kernels scale operands so that |value| <= 2^14.5 and
-   the lo halves stay normal.  K a multiple of 16 in [16, 4096]. */
+   the lo halves stay normal.  K a multiple of 16 in [16, 4096].
+
+   lsp_probe_cpair: the same operands through the conjugate-pair products of
+   the plain and generalized periodograms' default kernels: the four real
+   products A = sum Lr Rr, B = sum Li Ri, C = sum Lr Ri, D = sum Li Rr kept in
+   separate accumulators (three FP16 passes each), then
+   Pp = sum_j L[a][j] R[b][j] = (A - B, C + D) and
+   Pm = sum_j L[a][j] conj(R[b][j]) = (A + B, D - C); Pp, Pm: FP32 complex
+   [32][32]. */
 lsp_status lsp_probe_sincos(const float *r, int64_t n, float *s, float *c, void *stream);
 lsp_status lsp_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int32_t phase,
                            float *phi, void *stream);
 lsp_status lsp_probe_recurrence(const double *t, int64_t n, double t_ref, double f0, double step_df,
                                 int32_t M, float *c, float *s, void *stream);
 lsp_status lsp_probe_cmac(const float *L, const float *R, int32_t K, float *P, void *stream);
+lsp_status lsp_probe_cpair(const float *L, const float *R, int32_t K, float *Pp, float *Pm, void *stream);
 
 /* ---- profiling hook ------------------------------------------------------------
 

@@ -112,6 +112,7 @@ SIGNATURES = {
     "lsp_probe_phase": (_I32, [_P, _P, _I64, _D, _I32, _P, _P]),
     "lsp_probe_recurrence": (_I32, [_P, _I64, _D, _D, _D, _I32, _P, _P, _P]),
     "lsp_probe_cmac": (_I32, [_P, _P, _I32, _P, _P]),
+    "lsp_probe_cpair": (_I32, [_P, _P, _I32, _P, _P, _P]),
     "lsp_profile_enable": (_I32, [_I32]),
     "lsp_profile_read": (_I32, [ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.c_char_p, _I32]),
     "lsp_grid_paper": (_I32, [_D, _D, _I64, _D, _D, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
@@ -549,6 +550,22 @@ def lsp_probe_cmac(L, R, stream=None):
     _check(lib().lsp_probe_cmac(_ptr(L), _ptr(R), int(L.shape[1]), _ptr(P), _stream_ptr(stream)),
            "lsp_probe_cmac")
     return P
+
+
+def lsp_probe_cpair(L, R, stream=None):
+    """(sum_j L[a][j] R[b][j], sum_j L[a][j] conj(R[b][j])) by the conjugate-pair
+    products (device complex64 L, R of shape [32, K], K a multiple of 16):
+    two complex64 [32, 32]."""
+    torch = _torch()
+    _dev_tensor(L, torch.complex64, "L")
+    _dev_tensor(R, torch.complex64, "R")
+    if L.ndim != 2 or L.shape[0] != 32 or R.shape != L.shape:
+        raise ValueError("L and R must both be [32, K]")
+    Pp = torch.empty((32, 32), dtype=torch.complex64, device=L.device)
+    Pm = torch.empty((32, 32), dtype=torch.complex64, device=L.device)
+    _check(lib().lsp_probe_cpair(_ptr(L), _ptr(R), int(L.shape[1]), _ptr(Pp), _ptr(Pm), _stream_ptr(stream)),
+           "lsp_probe_cpair")
+    return Pp, Pm
 
 
 def lsp_profile_enable(on: bool = True):

@@ -189,6 +189,7 @@ hipError_t launch_probe_recur(const double *t, int64_t n, double t_ref, double f
                               float *s, hipStream_t st);
 int probe_recur_max();
 hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hipStream_t s);
+hipError_t launch_probe_cpair(const float *L, const float *R, int K, float *Pp, float *Pm, hipStream_t s);
 
 // records a message for lsp_last_error() on this host thread (lsp_host.cpp)
 // device address and size of this GPU's fixed scratch array (noalloc.hip);

@@ -1093,6 +1093,19 @@ lsp_status lsp_probe_cmac(const float *L, const float *R, int32_t K, float *P, v
     return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
 }
 
+lsp_status lsp_probe_cpair(const float *L, const float *R, int32_t K, float *Pp, float *Pm, void *stream)
+{
+    g_last_error.clear();
+    if (!L || !R || !Pp || !Pm || K < 16 || K > 4096 || K % 16 != 0) {
+        g_last_error = "invalid argument";
+        return LSP_ERR_INVALID_ARG;
+    }
+    lsp_status st = probe_device();
+    if (st != LSP_OK) return st;
+    hipError_t e = launch_probe_cpair(L, R, K, Pp, Pm, (hipStream_t)stream);
+    return e == hipSuccess ? LSP_OK : hip_fail(e, "probe launch");
+}
+
 lsp_status lsp_probe_phase(const double *t, const double *f, int64_t n, double t_ref, int32_t phase, float *phi,
                            void *stream)
 {

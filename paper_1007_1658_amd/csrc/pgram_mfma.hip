@@ -746,6 +746,47 @@ __global__ void __launch_bounds__(64) probe_cmac_kernel(const float *__restrict_
     }
 }
 
+// The same operands through the conjugate-pair products of the plain and
+// generalized kernels: the four real products accumulated apart (LSP_PMAC),
+// then Pp = sum L R = (A - B, C + D) and Pm = sum L conj(R) = (A + B, D - C).
+__global__ void __launch_bounds__(64) probe_cpair_kernel(const float *__restrict__ L, const float *__restrict__ R,
+                                                         int K, float *__restrict__ Pp, float *__restrict__ Pm)
+{
+    const int lane = threadIdx.x;
+    const int half = lane >> 5;
+    const int row = lane & 31;
+    const float one = opaque_one();
+    floatx16 A = floatx16{}, B = floatx16{}, C = floatx16{}, D = floatx16{};
+    for (int j0 = 0; j0 < K; j0 += 16) {
+        const int js = j0 + 8 * half;
+        COp X, Y;
+#pragma unroll
+        for (int i = 0; i < 8; i += 2) {
+            const float *la = L + 2 * ((int64_t)row * K + js + i);
+            const float *rb = R + 2 * ((int64_t)row * K + js + i);
+            X.set_cprod(i / 2, one, la[0], la[1], one, la[2], la[3]);
+            Y.set_cprod(i / 2, one, rb[0], rb[1], one, rb[2], rb[3]);
+        }
+        LSP_PMAC(X, Y.rh, Y.rl, Y.ih, Y.il, A, B, C, D);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int a = 8 * (r / 4) + 4 * half + (r % 4);
+        float *op = Pp + 2 * (a * 32 + row);
+        float *om = Pm + 2 * (a * 32 + row);
+        op[0] = A[r] - B[r];
+        op[1] = C[r] + D[r];
+        om[0] = A[r] + B[r];
+        om[1] = D[r] - C[r];
+    }
+}
+
+hipError_t launch_probe_cpair(const float *L, const float *R, int K, float *Pp, float *Pm, hipStream_t s)
+{
+    hipLaunchKernelGGL(probe_cpair_kernel, dim3(1), dim3(64), 0, s, L, R, K, Pp, Pm);
+    return hipGetLastError();
+}
+
 hipError_t launch_probe_cmac(const float *L, const float *R, int K, float *P, hipStream_t s)
 {
     hipLaunchKernelGGL(probe_cmac_kernel, dim3(1), dim3(64), 0, s, L, R, K, P);

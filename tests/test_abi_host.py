@@ -107,6 +107,9 @@ def test_probe_validation_on_host():
     for args in ((null, fake, 16, fake), (fake, fake, 8, fake), (fake, fake, 24, fake), (fake, fake, 8192, fake),
                  (fake, fake, 16, null)):
         assert L.lsp_probe_cmac(*args, null) == lsp.LSP_ERR_INVALID_ARG, args
+    for args in ((null, fake, 16, fake, fake), (fake, fake, 8, fake, fake), (fake, fake, 16, fake, null),
+                 (fake, fake, 8192, fake, fake)):
+        assert L.lsp_probe_cpair(*args, null) == lsp.LSP_ERR_INVALID_ARG, args
 
 
 def test_generalized_periodogram_validation_on_host():

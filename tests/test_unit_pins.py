@@ -172,3 +172,32 @@ def test_matrix_core_complex_product(K, kind):
     err = np.abs(P.astype(np.complex128) - ref) / scale
     print(f"cmac K={K} {kind}: max |dP| / sum|L||R| = {err.max():.3e} (2^{np.log2(err.max()):.1f})", flush=True)
     assert err.max() <= 2.0 ** -20
+
+
+@pytest.mark.parametrize("K,kind", [(16, "unit"), (2048, "unit"), (64, "scaled"), (256, "mixed")])
+def test_matrix_core_conjugate_pair_products(K, kind):
+    """The conjugate-pair form (four real products kept apart, combined as
+    L R and L conj(R)) against complex128, to the same per-element bar as the
+    complex product above.  A swapped sign in either combination, or
+    the imaginary parts' real products exchanged, fails by orders of
+    magnitude."""
+    g = np.random.default_rng([43, K, len(kind)])
+    ph_l = g.uniform(-0.5, 0.5, (32, K))
+    ph_r = g.uniform(-0.5, 0.5, (32, K))
+    if kind == "unit":
+        amp_l, amp_r = np.ones((32, K)), np.ones((32, K))
+    elif kind == "scaled":
+        amp_l = 2.0 ** 14 * g.uniform(0.0, 1.0, (32, K))
+        amp_r = np.full((32, K), 2.0 ** 14)
+    else:
+        amp_l = 10.0 ** g.uniform(-3, 3, (32, K))
+        amp_r = 10.0 ** g.uniform(-3, 3, (32, K))
+    Lh = (amp_l * np.exp(2j * np.pi * ph_l)).astype(np.complex64)
+    Rh = (amp_r * np.exp(2j * np.pi * ph_r)).astype(np.complex64)
+    Pp, Pm = lsp.lsp_probe_cpair(torch.from_numpy(Lh).cuda(), torch.from_numpy(Rh).cuda())
+    L64, R64 = Lh.astype(np.complex128), Rh.astype(np.complex128)
+    scale = np.abs(L64) @ np.abs(R64).T
+    for got, ref, name in ((Pp, L64 @ R64.T, "L R"), (Pm, L64 @ np.conj(R64).T, "L conj(R)")):
+        err = np.abs(got.cpu().numpy().astype(np.complex128) - ref) / scale
+        print(f"cpair K={K} {kind} {name}: max |dP| / sum|L||R| = {err.max():.3e}", flush=True)
+        assert err.max() <= 2.0 ** -20
