@@ -64,8 +64,8 @@ def MH_FLOP_PER_TERM(K):
     return 24 * K - 1
 # what the matrix pipe issues per term: three complex products in three FP16
 # passes (36 multiply-adds) per harmonic; half that per term for the
-# generalized periodogram's conjugate-pair kernel, whose products serve two
-# frequencies each
+# conjugate-pair kernels (the multi-harmonic ones and the generalized
+# periodogram's default), whose products serve two frequencies each
 ISSUED_FLOP_PER_HARMONIC = 72
 
 
@@ -344,7 +344,7 @@ def run_gls(args):
     k_avg_s = k_ms / 1e3 / max(k_n, 1)
     terms = c.Nt * c.Nf
     flop = MH_FLOP_PER_TERM(K) if mh else GLS_FLOP_PER_TERM
-    issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1) // (2 if k_name == "gls_pm_kernel" else 1)
+    issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1) // (2 if (mh or k_name == "gls_pm_kernel") else 1)
     achieved = flop * terms / k_avg_s / 1e12
     line = {
         "metric": (f"Nt·Nf terms/s of the multi-harmonic (K={K}) periodogram at max|Δp|≤1e-4" if mh else

@@ -145,6 +145,7 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 hipError_t launch_mh(const PgramArgs &a, int K, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1);
 constexpr int kGlsFreqPerWave = 32 * 32;      // generalized periodogram, 8-wave workgroups
 constexpr int kGlsPmFreqPerWave = 32 * 64;    // the same on conjugate pairs (up to 4 waves)
+constexpr int kMhFreqPerWave = 32 * 64;       // multi-harmonic periodogram (conjugate pairs)
 // FP64 recomputation of listed bins: workgroups of the pass (a listed bin is
 // split over up to kRefineMaxParts of them when few bins are listed)
 constexpr int kRefineBlocks = 256;

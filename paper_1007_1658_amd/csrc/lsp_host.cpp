@@ -893,11 +893,12 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     if (st != LSP_OK) return st;
     if (waves == 0) waves = 4;
     if (splits == 0) {
-        // GLS with up to 4 waves: conjugate pairs, one wave per SIMD, 64
-        // frequencies per a-row
-        const bool pm = K == 1 && waves <= 4;
-        splits = heuristic_splits(Nt, Nf, (pm ? kGlsPmFreqPerWave : kGlsFreqPerWave) / kWave, di->cus, waves,
-                                  pm ? 4 / waves : 2);
+        // up to 4 waves: conjugate pairs, one wave per SIMD, 64 frequencies
+        // per a-row (the multi-harmonic kernels always; GLS with 8 waves:
+        // complex products, 32 per a-row)
+        const bool pm = waves <= 4;
+        const int per_wave = (K == 1) ? (pm ? kGlsPmFreqPerWave : kGlsFreqPerWave) : kMhFreqPerWave;
+        splits = heuristic_splits(Nt, Nf, per_wave / kWave, di->cus, waves, pm ? 4 / waves : 2);
     }
     int64_t chunk = 0;
     int eff = 1;

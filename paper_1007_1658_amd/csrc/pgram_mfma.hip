@@ -1108,13 +1108,14 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
 
 // One pass: weight sums of harmonics W0..W1 (none when W1 < W0) and value sums
 // of harmonics 1..V (none when V = 0).
-template <int W0, int W1, int V>
+template <int W0, int W1, int V0, int V1>
 struct MhPass {
-    static constexpr int NW = (W1 >= W0) ? W1 - W0 + 1 : 0;
-    static constexpr int NS = NW + V;
-    static constexpr int HMAX = (W1 > V) ? W1 : V;
-    static constexpr bool weight(int m) { return m >= W0 && m <= W1; }
-    static constexpr bool value(int m) { return m >= 1 && m <= V; }
+    static constexpr int NW = (W1 >= W0) ? W1 - W0 + 1 : 0;  // weight harmonics W0..W1
+    static constexpr int NV = (V1 >= V0) ? V1 - V0 + 1 : 0;  // value harmonics V0..V1
+    static constexpr int NS = NW + NV;
+    static constexpr int HMAX = (W1 > V1) ? W1 : V1;
+    static constexpr bool weight(int m) { return NW > 0 && m >= W0 && m <= W1; }
+    static constexpr bool value(int m) { return NV > 0 && m >= V0 && m <= V1; }
     static constexpr bool needed(int m) { return weight(m) || value(m); }
     static constexpr int rslot(int m)
     {
@@ -1122,10 +1123,10 @@ struct MhPass {
         for (int i = 1; i < m; ++i) r += needed(i) ? 1 : 0;
         return r;
     }
-    static constexpr int wslot(int m) { return m - W0; }      // accumulator of weight harmonic m
-    static constexpr int vslot(int h) { return NW + h - 1; }  // accumulator of value harmonic h
-    static constexpr int NR = rslot(HMAX + 1);                // harmonics with R operands in LDS
-    static_assert(NS >= 1 && NS <= 6, "a pass holds one to six complex sums");
+    static constexpr int wslot(int m) { return m - W0; }       // accumulators of weight harmonic m
+    static constexpr int vslot(int h) { return NW + h - V0; }  // accumulators of value harmonic h
+    static constexpr int NR = rslot(HMAX + 1);                 // harmonics with R operands in LDS
+    static_assert(NS >= 1 && NS <= 3, "a pass holds one to three complex sums");
 };
 
 template <int NR>
@@ -1165,13 +1166,14 @@ struct MhRBuild {
     }
 };
 
-// the products of harmonic M over this lane's 8 samples, then the next harmonic
+// the products of harmonic M over this lane's 8 samples, then the next
+// harmonic: each complex sum as its four real products (conjugate pairs)
 template <class P, int M>
 struct MhStep {
     __device__ __forceinline__ static void run(const float (&e1r)[8], const float (&e1i)[8], float (&er)[8],
                                                float (&ei)[8], const float (&xv)[8], const float (&wv)[8],
                                                const MhLds<P::NR> &S, int row, int js,
-                                               floatx16 (&acc)[P::NS][2])
+                                               floatx16 (&acc)[P::NS][4])
     {
         if constexpr (M > 1) {
 #pragma unroll
@@ -1188,16 +1190,14 @@ struct MhStep {
                 COp LW;
 #pragma unroll
                 for (int i = 0; i < 8; i += 2) LW.set_cprod(i / 2, wv[i], er[i], ei[i], wv[i + 1], er[i + 1], ei[i + 1]);
-                LW.finish();
-                LSP_CMAC(LW, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
+                LSP_PMAC(LW, rrh, rrl, rih, ril, acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
             }
             if constexpr (P::value(M)) {
                 constexpr int q = P::vslot(M);
                 COp LX;
 #pragma unroll
                 for (int i = 0; i < 8; i += 2) LX.set_cprod(i / 2, xv[i], er[i], ei[i], xv[i + 1], er[i + 1], ei[i + 1]);
-                LX.finish();
-                LSP_CMAC(LX, rrh, rrl, rih, ril, acc[q][0], acc[q][1]);
+                LSP_PMAC(LX, rrh, rrl, rih, ril, acc[q][0], acc[q][1], acc[q][2], acc[q][3]);
             }
         }
         if constexpr (M < P::HMAX) MhStep<P, M + 1>::run(e1r, e1i, er, ei, xv, wv, S, row, js, acc);
@@ -1205,12 +1205,16 @@ struct MhStep {
 };
 
 // Per-chunk partial sums of one pass, written to the slots of the K-harmonic
-// layout: sum q (0..3K-1) = weight harmonic q + 1 for q < 2K, value harmonic
-// q - 2K + 1 after that; its real and imaginary parts at slots 2q and 2q + 1.
-template <int K, int W0, int W1, int V>
+// layout: sum g (0..3K-1) = weight harmonic g + 1 for g < 2K, value harmonic
+// g - 2K + 1 after that; its real and imaginary parts at slots 2g and 2g + 1.
+// Conjugate pairs as in mfma_sums_pm: F_a = f_min + (64 a + 31.5) df,
+// harmonic m of beta_b = (b + 1/2) df, and each sum's four real products give
+// frequencies k = 64 a + 32 + b and 64 a + 31 - b.  At most three complex
+// sums (twelve accumulators) per pass, one wave per SIMD.
+template <int K, int W0, int W1, int V0, int V1>
 __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 {
-    using P = MhPass<W0, W1, V>;
+    using P = MhPass<W0, W1, V0, V1>;
     constexpr int NS = P::NS;
     __shared__ MhLds<P::NR> S;
     const int tid = threadIdx.x;
@@ -1248,14 +1252,13 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
     const float wscale = ldexpf(1.0f, 14 - ew);
 
     const int64_t a_row = ((int64_t)blockIdx.x * nw + wave) * 32 + row;
-    const double Fa = a.f_min + (double)(a_row * 32) * a.df;
+    const double Fa = a.f_min + ((double)(a_row * 64) + 31.5) * a.df;
 
-    floatx16 acc[NS][2];  // [sum][re, im], sums in the pass's order (weights, then values)
+    floatx16 acc[NS][4];  // [sum][A, B, C, D], sums in the pass's order (weights, then values)
 #pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        acc[q][0] = floatx16{};
-        acc[q][1] = floatx16{};
-    }
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[q][c] = floatx16{};
 
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();
@@ -1272,7 +1275,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
         for (int task = tid; task < 32 * (kMB / 8); task += blockDim.x) {
             const int b = task / (kMB / 8);
             const int g = task % (kMB / 8);
-            const double bdf = (double)b * a.df;
+            const double bdf = ((double)b + 0.5) * a.df;
             halfx8 v[4 * P::NR];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
@@ -1307,15 +1310,22 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
         const int64_t ar = ((int64_t)blockIdx.x * nw + wave) * 32 + 8 * (r / 4) + 4 * half + (r % 4);
-        const int64_t k = ar * 32 + row;
-        if (k < a.Nf) {
-            float *p = a.part + (int64_t)split * 6 * K * a.Nf + k;
 #pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                const int gq = (q < P::NW) ? (W0 - 1 + q) : (2 * K + q - P::NW);
-                const float u = (q < P::NW) ? uw : ux;
-                p[(int64_t)(2 * gq) * a.Nf] = acc[q][0][r] * u;
-                p[(int64_t)(2 * gq + 1) * a.Nf] = acc[q][1][r] * u;
+        for (int n = 0; n < 2; ++n) {
+            // n = 0: F_a + beta_b (L R), n = 1: F_a - beta_b (L conj(R))
+            const int64_t k = n == 0 ? ar * 64 + 32 + row : ar * 64 + 31 - row;
+            if (k < a.Nf) {
+                const float sg = n == 0 ? -1.0f : 1.0f;
+                float *p = a.part + (int64_t)split * 6 * K * a.Nf + k;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int gq = (q < P::NW) ? (W0 - 1 + q) : (2 * K + V0 - 1 + q - P::NW);
+                    const float u = (q < P::NW) ? uw : ux;
+                    const float re = acc[q][0][r] + sg * acc[q][1][r];
+                    const float im = n == 0 ? acc[q][2][r] + acc[q][3][r] : acc[q][3][r] - acc[q][2][r];
+                    p[(int64_t)(2 * gq) * a.Nf] = re * u;
+                    p[(int64_t)(2 * gq + 1) * a.Nf] = im * u;
+                }
             }
         }
     }
@@ -1590,20 +1600,26 @@ hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s)
 template <int K>
 static hipError_t launch_mh_k(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1)
 {
-    const int64_t per_wave = 32 * 32;
+    const int64_t per_wave = kMhFreqPerWave;
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + waves - 1) / waves;
     const dim3 grid((unsigned)nblk, (unsigned)a.splits), block(kWave * waves);
     if (ev0) hipEventRecord(ev0, s);
+    // passes of at most three complex sums: weight harmonics 1..2K, then the
+    // value harmonics 1..K
     if constexpr (K == 2) {
-        hipLaunchKernelGGL((mh_mfma_kernel<2, 1, 4, 2>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<2, 1, 3, 1, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<2, 4, 4, 1, 2>), grid, block, 0, s, a);
     } else if constexpr (K == 3) {
-        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 6, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 0, 3>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 3, 1, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<3, 4, 6, 1, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 0, 1, 3>), grid, block, 0, s, a);
     } else {
         static_assert(K == 4, "K = 2, 3 or 4");
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 6, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 7, 8, 4>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 3, 1, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 4, 6, 1, 0>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 7, 8, 1, 1>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 0, 2, 4>), grid, block, 0, s, a);
     }
     if (ev1) hipEventRecord(ev1, s);
     hipError_t e = hipGetLastError();
