@@ -17,7 +17,7 @@
 // Operands are scaled by powers of two (values by 2^(14-e) with 2^e > max|x|
 // over the chunk, trigonometric factors by 2^14) so that the lo parts stay
 // in FP16's normal range; the scales are removed exactly at the end.
-// Phases are FP64 products reduced to revolutions (as the SPLIT mode).
+// Phases are FP64 products (as the SPLIT mode) reduced to [0, 1) revolutions.
 //
 // Work split: a workgroup of W waves owns a-rows [32 W blockIdx.x, +32 W) and
 // all b; wave w owns 32 a-rows (64 frequencies each).  Per block of 64
@@ -65,6 +65,11 @@ __device__ __forceinline__ void split16(float v, _Float16 &hi, _Float16 &lo)
     hi = (_Float16)v;
     lo = (_Float16)(v - (float)hi);
 }
+
+// A phase product reduced to [0, 1) revolutions by one v_fract_f64 (the
+// hardware sine and cosine take any such argument; one instruction fewer than
+// rounding to the nearest integer and subtracting it)
+__device__ __forceinline__ float rev_fract(double p) { return (float)__builtin_amdgcn_fract(p); }
 
 // 1.0f in a register the compiler cannot see into (an operand of the split
 // sequences below, which take their inputs in registers)
@@ -211,7 +216,7 @@ __device__ __forceinline__ void build_r8(double bdf, const double *t, float one,
         float c[2], s[2], tt[2], c2[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const float ph = rev_reduce(bdf * t[i + u]);
+            const float ph = rev_fract(bdf * t[i + u]);
             c[u] = cos_rev(ph);
             s[u] = sin_rev(ph);
             tt[u] = double_angle(c[u], kTrigScale, c2[u]);
@@ -235,7 +240,7 @@ __device__ __forceinline__ void build_r4(double bdf, const double *t, float one,
         float c[2], s[2], tt[2], c2[2];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const float ph = rev_reduce(bdf * t[i + u]);
+            const float ph = rev_fract(bdf * t[i + u]);
             c[u] = cos_rev(ph);
             s[u] = sin_rev(ph);
             tt[u] = double_angle(c[u], kTrigScale, c2[u]);
@@ -359,7 +364,7 @@ __device__ __forceinline__ void gls_sums(const PgramArgs &a)
                 float c[2], s[2], t[2], c2[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    const float ph = rev_fract(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
                     t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
@@ -544,7 +549,7 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
                 float c[2], s[2], t[2], c2[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    const float ph = rev_fract(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
                     t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
@@ -664,7 +669,7 @@ __device__ __forceinline__ void gls_sums_pm(const PgramArgs &a)
                 float c[2], s[2], t[2], c2[2];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
-                    const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                    const float ph = rev_fract(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
                     t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
@@ -936,7 +941,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                     float c[2], s[2], t[2], c2[2];
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
-                        const float ph = rev_reduce(Fa * S.t[js + i + u]);
+                        const float ph = rev_fract(Fa * S.t[js + i + u]);
                         c[u] = cos_rev(ph);
                         s[u] = sin_rev(ph);
                         t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
@@ -1279,7 +1284,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
             halfx8 v[4 * P::NR];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float ph = rev_reduce(bdf * S.t[8 * g + i]);
+                const float ph = rev_fract(bdf * S.t[8 * g + i]);
                 const float c1 = cos_rev(ph), s1 = sin_rev(ph);
                 MhRBuild<P, 1>::run(c1, s1, c1, s1, v, i);
             }
@@ -1293,7 +1298,7 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
             float e1r[8], e1i[8], er[8], ei[8], xv[8], wv[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float ph = rev_reduce(Fa * S.t[js + i]);
+                const float ph = rev_fract(Fa * S.t[js + i]);
                 e1r[i] = cos_rev(ph);
                 e1i[i] = sin_rev(ph);
                 er[i] = e1r[i];
