@@ -81,12 +81,15 @@ typedef enum lsp_trig_mode {
        c_{m+1} = 2 cos(step) c_m - c_{m-1} (and likewise for sin).  Re-seeded
        exactly at every sample.  Only with LSP_PHASE_SPLIT / SPLIT32. */
     LSP_TRIG_RECUR = 2,
-    /* Matrix cores: with k = 64a + b, the sums of Eq. (8) are the complex
-       products sum_j [x_j e^{i w_a t'_j}] [e^{i b dw t'_j}] (and the same at
-       twice the angle for CC, CS), FP16 hi/lo operands in three passes with
-       FP32 accumulation (v_mfma_f32_32x32x16_f16); one sin/cos pair per
-       (a, j) and per (b, j).  Only with LSP_PHASE_SPLIT; m = 32 (a wave
-       covers 32 a-rows x 64 b = 2048 frequencies), unroll 1, sum TWO. */
+    /* Matrix cores: with w_a the centre of frequencies 64a .. 64a + 63 and
+       v_b = (b + 1/2) dw, b < 32, the sums of Eq. (8) at w_a +- v_b are the
+       complex products sum_j [x_j e^{i w_a t'_j}] [e^{i v_b t'_j}] and
+       sum_j [x_j e^{i w_a t'_j}] conj[e^{i v_b t'_j}] (and the same at twice
+       the angle for CC, CS), both from the same four real products; FP16
+       hi/lo operands in three passes with FP32 accumulation
+       (v_mfma_f32_32x32x16_f16); one sin/cos pair per (a, j) and per (b, j).
+       Only with LSP_PHASE_SPLIT; m = 32 (a wave covers 32 a-rows x 64
+       frequencies = 2048), unroll 1, sum TWO. */
     LSP_TRIG_MFMA = 3
 } lsp_trig_mode;
 
