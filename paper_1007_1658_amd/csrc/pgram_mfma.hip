@@ -1041,10 +1041,13 @@ constexpr double kRefinePivot = 1e-2;
 // FP64 sums (fp64 = true): the determinant or the direction <= 1e-12, the
 // oracle's rule.  *lmin: the smaller eigenvalue of [[CC, CS], [CS, SS]].
 __device__ __forceinline__ double gls_power(double C, double Sn, double YC, double YS, double C2, double S2,
-                                            double YY, bool fp64, double *lmin)
+                                            double YY, bool fp64, double *lmin, bool dform = false)
 {
+    // dform: C and C2 carried as C - 1 and C2 - 1 (see mh_power)
     const double CCh = 0.5 + 0.5 * C2, CSh = 0.5 * S2;
-    const double CC = CCh - C * C, SS = (1.0 - CCh) - Sn * Sn, CS = CSh - C * Sn;
+    const double CC = dform ? 0.5 * C2 - 2.0 * C - C * C : CCh - C * C;
+    const double SS = dform ? -0.5 * C2 - Sn * Sn : (1.0 - CCh) - Sn * Sn;
+    const double CS = dform ? CSh - (1.0 + C) * Sn : CSh - C * Sn;
     const double D = CC * SS - CS * CS;
     const double h = 0.5 * (CC - SS);
     *lmin = 0.5 * (CC + SS) - sqrt(h * h + CS * CS);
@@ -1349,11 +1352,15 @@ __global__ void __launch_bounds__(256, 1) mh_mfma_kernel(PgramArgs a)
 // pivot <= 1e-12 of the uncentred diagonal sum w u_i^2, the oracle's rule.
 // *min_pivot: the smallest pivot met (dropped columns included).
 template <int K>
-__device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64, double *min_pivot)
+__device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64, double *min_pivot,
+                                          bool dform = false)
 {
     constexpr int M2 = 2 * K, n = 2 * K;
+    // dform: the cosine sums are carried as C_m - 1 (d_m), which keeps the
+    // centred Gram entries of low frequencies (wt << 1 over the baseline, where
+    // C_m - C_A C_B cancels to O((wt)^4)) to FP64 precision relative to them
     double C[M2 + 1], Sn[M2 + 1];
-    C[0] = 1.0;
+    C[0] = dform ? 0.0 : 1.0;
     Sn[0] = 0.0;
 #pragma unroll
     for (int m = 1; m <= M2; ++m) {
@@ -1367,7 +1374,7 @@ __device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64
 #pragma unroll
     for (int i = 0; i < n; ++i) {
         const int h = 1 + i / 2;
-        mean[i] = (i % 2 == 0) ? C[h] : Sn[h];
+        mean[i] = (i % 2 == 0) ? C[h] : Sn[h];  // dform: the cosine means less 1
         b[i] = v[2 * M2 + 2 * (h - 1) + (i % 2)];
     }
 #pragma unroll
@@ -1375,13 +1382,24 @@ __device__ __forceinline__ double mh_power(const double *v, double YY, bool fp64
 #pragma unroll
         for (int j = 0; j <= i; ++j) {
             const int A = 1 + i / 2, B = 1 + j / 2;
+            const bool ci = i % 2 == 0, cj = j % 2 == 0;
             double r;
-            if (i % 2 == 0 && j % 2 == 0) r = 0.5 * (Cm(A - B) + Cm(A + B));
-            else if (i % 2 == 1 && j % 2 == 1) r = 0.5 * (Cm(A - B) - Cm(A + B));
-            else if (i % 2 == 0) r = 0.5 * (Sm(A + B) - Sm(A - B));  // cos(A) sin(B)
-            else r = 0.5 * (Sm(A + B) + Sm(A - B));                   // sin(A) cos(B)
-            if (i == j) raw[i] = r;
-            G[i][j] = r - mean[i] * mean[j];
+            if (ci && cj) r = 0.5 * (Cm(A - B) + Cm(A + B));
+            else if (!ci && !cj) r = 0.5 * (Cm(A - B) - Cm(A + B));
+            else if (ci) r = 0.5 * (Sm(A + B) - Sm(A - B));  // cos(A) sin(B)
+            else r = 0.5 * (Sm(A + B) + Sm(A - B));          // sin(A) cos(B)
+            if (!dform) {
+                if (i == j) raw[i] = r;
+                G[i][j] = r - mean[i] * mean[j];
+            } else {
+                // with C = 1 + d: E[cos cos] = 1 + r and mean = 1 + d, so the
+                // centred entry is r - d_A - d_B - d_A d_B; cos sin: r - (1 + d_A) s_B
+                if (i == j) raw[i] = ci ? 1.0 + r : r;
+                if (ci && cj) G[i][j] = r - mean[i] - mean[j] - mean[i] * mean[j];
+                else if (!ci && !cj) G[i][j] = r - mean[i] * mean[j];
+                else if (ci) G[i][j] = r - (1.0 + mean[i]) * mean[j];
+                else G[i][j] = r - mean[i] * (1.0 + mean[j]);
+            }
         }
     const double eps = 1e-5;
     double z[n];
@@ -1446,7 +1464,11 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 // tid + 256, ... from the records the matrix-core kernels read (t' = th + tl,
 // w/W, w (y - Y)/W), with the phase reduced and the sine and cosine evaluated
 // in FP64 and the harmonics by complex products; a fixed-order tree adds the
-// threads' sums, then the solve runs with the FP64 rule.  A bin takes one
+// threads' sums, then the solve runs with the FP64 rule.  The harmonics are
+// carried as e^{i m theta} - 1 (from the half angle), so that the cosine sums
+// are C_m - 1: at frequencies with less than a cycle over the baseline the
+// centred Gram entries are O((wt)^4) and would cancel against the raw sums'
+// O(1) to FP64 rounding.  A bin takes one
 // workgroup, or, when few bins are listed (typically only f = 0), P of them
 // over consecutive sample ranges, whose sums a second kernel adds in range
 // order; P depends only on the number of listed bins, so a bin's value does
@@ -1455,9 +1477,9 @@ __global__ void __launch_bounds__(256) mh_reduce_kernel(const float *__restrict_
 // so their own totals W0 = sum w/W and Y0 = sum w (y - Y)/W (summed alongside,
 // in the same order) differ from 1 and 0 by rounding: every weight sum is
 // divided by W0 and every value sum is centred on Y0/W0, which makes the
-// normal equations those of the records' own weights exactly (at f = 0 the
-// cosine sums then equal their weight total bit for bit, and the constant
-// direction is dropped as the oracle drops it).
+// normal equations those of the records' own weights exactly (at f = 0 every
+// sum of e^{i m theta} - 1 is 0, and the constant direction is dropped as the
+// oracle drops it).
 // workgroups per listed bin: the pass's kRefineBlocks workgroups spread over
 // the n listed bins, at most kRefineMaxParts each (1: a workgroup per bin,
 // which then also evaluates the power)
@@ -1482,7 +1504,8 @@ __device__ __forceinline__ float refine_power(double *v, double YY)
     double d;
     double p = 0.0;
     if (W0 > 0.0)
-        p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d) : mh_power<K>(v, YY, true, &d);
+        p = (K == 1) ? gls_power(v[0], v[1], v[4], v[5], v[2], v[3], YY, true, &d, true)
+                     : mh_power<K>(v, YY, true, &d, true);
     return (float)p;
 }
 
@@ -1511,22 +1534,26 @@ __global__ void __launch_bounds__(256) mh_refine_kernel(PgramArgs a)
             const double tp = (double)a.rec.th[j] + (double)a.rec.tl[j];
             double ph = f * tp;
             ph -= rint(ph);
-            double s1, c1;
-            sincospi(2.0 * ph, &s1, &c1);
+            // e^{i m theta} - 1 = u_m + i v_m, from the half angle without
+            // cancellation: u_1 = -2 sin^2(theta/2), v_1 = sin theta, then
+            // (1 + u_m + i v_m)(1 + u_1 + i v_1) with the 1 kept out
+            double sh, ch;
+            sincospi(ph, &sh, &ch);
+            const double u1 = -2.0 * sh * sh, v1 = 2.0 * sh * ch;
             const double w = (double)a.rec.wv[j], y = (double)a.rec.xv[j];
-            double cr = c1, ci = s1;
+            double u = u1, vv = v1;
 #pragma unroll
             for (int m = 1; m <= 2 * K; ++m) {
                 if (m > 1) {
-                    const double r = cr * c1 - ci * s1;
-                    ci = cr * s1 + ci * c1;
-                    cr = r;
+                    const double un = u + u1 + (u * u1 - vv * v1);
+                    vv = vv + v1 + (u * v1 + vv * u1);
+                    u = un;
                 }
-                v[2 * (m - 1)] += w * cr;
-                v[2 * (m - 1) + 1] += w * ci;
+                v[2 * (m - 1)] += w * u;
+                v[2 * (m - 1) + 1] += w * vv;
                 if (m <= K) {
-                    v[4 * K + 2 * (m - 1)] += y * cr;
-                    v[4 * K + 2 * (m - 1) + 1] += y * ci;
+                    v[4 * K + 2 * (m - 1)] += y * u;
+                    v[4 * K + 2 * (m - 1) + 1] += y * vv;
                 }
             }
             v[NS] += w;

@@ -145,3 +145,43 @@ def test_weighted_fit_on_degenerate_bins_every_bin(K):
     assert err <= REL_TOL
     assert peak_matches(Pg.cpu().numpy(), P)
     assert torch.equal(run(), Pg)
+
+
+@pytest.mark.parametrize("K,Nf,band", [(1, 40, None), (1, 700, (0.02, 0.58)), (2, 300, (0.3, 1.5)),
+                                        (2, 600, (0.1, 1.5))])
+def test_fp64_recomputation_partitions(K, Nf, band):
+    """Frequencies of less than about a cycle over the baseline T make the
+    normal equations ill-conditioned, so the FP64 recomputation gets from a
+    few bins (the paper's grid, df = 1/(4T): each split over several
+    workgroups, whose sums a second kernel adds in order) to several hundred
+    (band f T in [lo, hi] over Nf bins: one workgroup per bin, more bins than
+    workgroups).  The bands stop where the FP64 oracle itself still agrees
+    with an independent centred least-squares solve (to 7e-9 of max p);
+    below f T ~ 0.02 the oracle's raw-moment sums lose the cosine column.
+    Every bin against the oracle, the physical range, and reruns bitwise
+    equal."""
+    g = np.random.default_rng([59, K, Nf])
+    Nt = 50
+    t = np.sort(g.uniform(0.0, 10.0, Nt))
+    y = (np.sin(2 * np.pi * 0.03 * t) + g.normal(0.0, 1.0, Nt)).astype(np.float32)
+    w = g.uniform(0.5, 2.0, Nt).astype(np.float32)
+    T = t[-1] - t[0]
+    if band is None:
+        df = 1.0 / (4 * T)
+        f_min = df
+    else:
+        f_min, df = band[0] / T, (band[1] - band[0]) / T / Nf
+    td, yd, wd = _dev(t, y, w)
+    if K == 1:
+        P = oracle.gls(t, y.astype(np.float64), f_min, df, Nf=Nf, w=w.astype(np.float64))
+        run = lambda: lsp.lsp_gls(td, yd, f_min, df, Nf, w=wd)
+    else:
+        P = oracle.multiharmonic(t, y.astype(np.float64), K, f_min, df, Nf=Nf, w=w.astype(np.float64))
+        run = lambda: lsp.lsp_multiharmonic(td, yd, K, f_min, df, Nf, w=wd)
+    Pg = run()
+    pg = Pg.cpu().numpy()
+    err = rel_err(pg, P)
+    print(f"refine partitions K={K} Nf={Nf} band={band}: every-bin rel err {err:.3e}", flush=True)
+    assert err <= REL_TOL
+    assert np.all(pg >= 0.0) and np.all(pg <= 1.0)
+    assert torch.equal(run(), Pg)
