@@ -455,10 +455,11 @@ def main():
         if args.save_tune:
             lsp.lsp_tune_cache_save(args.save_tune)
 
-    # the VALU form's fastest whole call on c1 in a sweep of the built recurrence
-    # shapes (M, unroll, summation, waves, splits): two-level FP32 sums, whose
-    # error on c1 matches the compensated ones (both ~2e-6 of the sampled max)
-    valu_kw = dict(trig="recur", m=14, unroll=2, sum="two", waves=4, splits=62 if curve.Nt >= 1 << 15 else 0)
+    # the VALU form's fastest whole call on c1 in sweeps of the built recurrence
+    # shapes (M, unroll, summation, waves, splits in steps of 4): two-level FP32
+    # sums, whose error on c1 matches the compensated ones (both ~2e-6 of the
+    # sampled max); 72 splits of 37 frequency tiles fill the CUs in whole rounds
+    valu_kw = dict(trig="recur", m=14, unroll=2, sum="two", waves=4, splits=72 if curve.Nt >= 1 << 15 else 0)
     if args.form == "valu":
         # the FP32-VALU form as the timed line (frequency recurrence)
         tile = {"trig": lsp.LSP_TRIG_RECUR, "m": 14, "waves": 4, "splits": valu_kw["splits"], "unroll": 2,

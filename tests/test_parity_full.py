@@ -27,7 +27,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 import paper_1007_1658_amd as lsp  # noqa: E402
 
 # the FP32-VALU launch the benchmark times beside the default one
-VALU = dict(trig="recur", m=14, unroll=2, sum="two", waves=4, splits=62)
+VALU = dict(trig="recur", m=14, unroll=2, sum="two", waves=4, splits=72)
 
 FORMS = {
     "default": {},
