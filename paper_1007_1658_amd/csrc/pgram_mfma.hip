@@ -55,7 +55,7 @@ template <int NB, bool GLS>
 struct MfmaLds {
     double t[kMB];
     float x[kMB];
-    float w[kMB];  // GLS: weights; plain: the double-angle scale, 0 for pads
+    float w[kMB];  // GLS: weights; plain: the scale of the R2 operands, 0 for pads
     float red[2][kMfmaMaxWaves];
     alignas(16) _Float16 R[R_KINDS][32 * NB][kMRow];  // 16-B rows: whole-row b128 reads and writes
 };
@@ -207,8 +207,10 @@ struct COp {
 };
 
 // R operands of 8 samples (times t[0..7], one b): R = 2^14 e^{2 pi i b df t'}
-// and R2 = 2^14 e^{4 pi i b df t'}, as hi/lo halves
-__device__ __forceinline__ void build_r8(double bdf, const double *t, float one, COp &R, COp &R2)
+// and R2 = g e^{4 pi i b df t'}, as hi/lo halves; g = g2[i] (0 for the pads
+// of a ragged block, so that they add nothing to the double-angle sums) or
+// 2^14 for g2 = nullptr
+__device__ __forceinline__ void build_r8(double bdf, const double *t, const float *g2, float one, COp &R, COp &R2)
 {
     const float scale = kTrigScale;
 #pragma unroll
@@ -219,7 +221,7 @@ __device__ __forceinline__ void build_r8(double bdf, const double *t, float one,
             const float ph = rev_fract(bdf * t[i + u]);
             c[u] = cos_rev(ph);
             s[u] = sin_rev(ph);
-            tt[u] = double_angle(c[u], kTrigScale, c2[u]);
+            tt[u] = double_angle(c[u], g2 ? g2[i + u] : kTrigScale, c2[u]);
         }
         R.set_cprod(i / 2, scale, c[0], s[0], scale, c[1], s[1]);
         R2.set_csum(i / 2, c2[0], c2[1], tt[0], s[0], tt[1], s[1], one);
@@ -229,8 +231,8 @@ __device__ __forceinline__ void build_r8(double bdf, const double *t, float one,
 // The same for 4 samples, written straight to the LDS staging area (row b,
 // samples s0 .. s0+3 of each operand kind)
 template <int NBR>
-__device__ __forceinline__ void build_r4(double bdf, const double *t, float one, _Float16 (&R)[R_KINDS][NBR][kMRow],
-                                         int b, int s0)
+__device__ __forceinline__ void build_r4(double bdf, const double *t, const float *g2, float one,
+                                         _Float16 (&R)[R_KINDS][NBR][kMRow], int b, int s0)
 {
     typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     u32x2 v[R_KINDS];
@@ -243,7 +245,7 @@ __device__ __forceinline__ void build_r4(double bdf, const double *t, float one,
             const float ph = rev_fract(bdf * t[i + u]);
             c[u] = cos_rev(ph);
             s[u] = sin_rev(ph);
-            tt[u] = double_angle(c[u], kTrigScale, c2[u]);
+            tt[u] = double_angle(c[u], g2 ? g2[i + u] : kTrigScale, c2[u]);
         }
         unsigned p, q, r, w;
         split_cprod2(scale, c[0], s[0], scale, c[1], s[1], p, q, r, w);
@@ -343,7 +345,7 @@ __device__ __forceinline__ void gls_sums(const PgramArgs &a)
             const int g = task % (kMB / 8);
             const double bdf = (double)b * a.df;
             COp R, R2;
-            build_r8(bdf, &S.t[8 * g], one, R, R2);
+            build_r8(bdf, &S.t[8 * g], nullptr, one, R, R2);
             *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
             *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
             *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
@@ -522,7 +524,7 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
             // scale of 0 so that they add nothing to CC
             S.t[tid] = pok ? (double)pth + (double)ptl : 0.0;
             S.x[tid] = pok ? pxv * xscale : 0.0f;
-            S.w[tid] = pok ? kTrigScale : 0.0f;
+            S.w[tid] = pok ? kTrigScale : 0.0f;  // R2 of the pads: 0
             const int64_t j = j0 + kMB + tid;
             pok = j < je;
             if (pok) {
@@ -537,7 +539,7 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
         for (int task = tid; task < 32 * (kMB / 4); task += blockDim.x) {
             const int b = task / (kMB / 4);
             const int g = task % (kMB / 4);
-            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], one, S.R, b, 4 * g);
+            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], &S.w[4 * g], one, S.R, b, 4 * g);
         }
         __syncthreads();
 #pragma unroll
@@ -552,7 +554,7 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
                     const float ph = rev_fract(Fa * S.t[js + i + u]);
                     c[u] = cos_rev(ph);
                     s[u] = sin_rev(ph);
-                    t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
+                    t[u] = double_angle(c[u], kTrigScale, c2[u]);
                 }
                 L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
                 L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
@@ -657,7 +659,7 @@ __device__ __forceinline__ void gls_sums_pm(const PgramArgs &a)
         for (int task = tid; task < 32 * (kMB / 4); task += blockDim.x) {
             const int b = task / (kMB / 4);
             const int g = task % (kMB / 4);
-            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], one, S.R, b, 4 * g);
+            build_r4(((double)b + 0.5) * a.df, &S.t[4 * g], nullptr, one, S.R, b, 4 * g);
         }
         __syncthreads();
 #pragma unroll
@@ -905,7 +907,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
             if (tid < kMB) {
                 S.t[tid] = pok ? (double)pth + (double)ptl : 0.0;
                 S.x[tid] = pok ? pxv * xscale : 0.0f;
-                S.w[tid] = pok ? kTrigScale : 0.0f;  // pads: L2 = 0
+                S.w[tid] = pok ? kTrigScale : 0.0f;  // pads: R2 = 0
                 const int64_t j = j0 + kMB + tid;
                 pok = j < Nt;
                 if (pok) {
@@ -920,7 +922,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                 const int g = task % (kMB / 8);
                 const double bdf = ((double)b + 0.5) * cv.df;
                 COp R, R2;
-                build_r8(bdf, &S.t[8 * g], one, R, R2);
+                build_r8(bdf, &S.t[8 * g], &S.w[8 * g], one, R, R2);
                 *reinterpret_cast<halfx8 *>(&S.R[RR_H][b][8 * g]) = R.rh;
                 *reinterpret_cast<halfx8 *>(&S.R[RR_L][b][8 * g]) = R.rl;
                 *reinterpret_cast<halfx8 *>(&S.R[RI_H][b][8 * g]) = R.ih;
@@ -944,7 +946,7 @@ __global__ void __launch_bounds__(256, 2) batch_mfma_kernel(BatchArgs a)
                         const float ph = rev_fract(Fa * S.t[js + i + u]);
                         c[u] = cos_rev(ph);
                         s[u] = sin_rev(ph);
-                        t[u] = double_angle(c[u], S.w[js + i + u], c2[u]);
+                        t[u] = double_angle(c[u], kTrigScale, c2[u]);
                     }
                     L.set_cprod(i / 2, S.x[js + i], c[0], s[0], S.x[js + i + 1], c[1], s[1]);
                     L2.set_csum(i / 2, c2[0], c2[1], t[0], s[0], t[1], s[1], one);
