@@ -9,8 +9,8 @@ data at scale: Monte-Carlo maxima (lsp_mc_maxpower), window features
 learning rates and chunk sizes, and it computes, once per trained model, a
 few numbers that the model file then carries: the feature standardization
 and the head's location scale (fit_scalers, moments of the training data),
-and the calibrated law errors (calibrate, a two-parameter least-squares fit
-to held-out residuals).  These are model-building arithmetic of the driver;
+and the calibrated law error (calibrate, set by coverage of held-out
+residuals).  These are model-building arithmetic of the driver;
 none of it runs when a FAP is served.
 
     python -m paper_1007_1658_amd.surrogate --out model.bin --report report.json
