@@ -59,6 +59,14 @@ struct PgramArgs {
     uint32_t *refine_list;   // [Nf]
     uint32_t *refine_count;  // [1], zeroed by the weighted prep
     double *refine_part;     // [kRefineBlocks][6 K + 2] partial FP64 sums of a bin split over workgroups
+    // single-curve matrix-core form: the raw series and the prep's partial
+    // moments; its kernel merges them, converts each sample as the record
+    // kernel would, and writes the curve's scalars for the merge
+    const double *t_raw;     // [Nt]
+    const float *x_raw;      // [Nt]
+    const Moments *mom;      // [n_mom]
+    int32_t n_mom;
+    CurveStats *stats_w;     // = stats, written by workgroup (0, 0)
 };
 
 // Batched work item: one wave computes 64*m frequencies of one curve.
@@ -154,6 +162,8 @@ constexpr int kRefineMaxParts = 32;
 hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s);
 
 // moments and CurveStats only (no records)
+hipError_t launch_moment_parts(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
+                               hipStream_t s);
 hipError_t launch_moments(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
                           CurveStats *stats, hipStream_t s);
 // extirpolation + FFT periodogram (fast_kernels.hip): grids = 2 N doubles (values, ones at 2u);

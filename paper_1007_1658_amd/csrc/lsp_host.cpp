@@ -352,11 +352,13 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     rec.rs = (float *)(base + L.rs);
     rec.wv = nullptr;
     CurveStats *stats = (CurveStats *)(base + L.stats);
-    // the step rotation records serve the recurrence form only; the matrix-core
-    // kernel reads the split times and values alone
-    const double step_df = (tile.trig == LSP_TRIG_MFMA) ? 0.0 : (double)kWave * df;
-    hipError_t e = launch_prep(t, x, Nt, step_df, phase, (Moments *)(base + L.moments), n_mom,
-                               stats, rec, s);
+    // the matrix-core kernel merges the partial moments and converts the raw
+    // samples itself; the other forms read records (the step rotations serve
+    // the recurrence form)
+    Moments *moments = (Moments *)(base + L.moments);
+    const bool mfma = tile.trig == LSP_TRIG_MFMA;
+    hipError_t e = mfma ? launch_moment_parts(t, x, Nt, moments, n_mom, s)
+                        : launch_prep(t, x, Nt, (double)kWave * df, phase, moments, n_mom, stats, rec, s);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
 
     PgramArgs a;
@@ -373,6 +375,11 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     a.refine_list = nullptr;
     a.refine_count = nullptr;
     a.refine_part = nullptr;
+    a.t_raw = mfma ? t : nullptr;
+    a.x_raw = mfma ? x : nullptr;
+    a.mom = mfma ? moments : nullptr;
+    a.n_mom = n_mom;
+    a.stats_w = stats;
 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (allow_profile && ctx().prof) {
@@ -952,6 +959,11 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     a.refine_list = (uint32_t *)(base + o_list);
     a.refine_count = refine_count;
     a.refine_part = (double *)(base + o_rpart);
+    a.t_raw = nullptr;
+    a.x_raw = nullptr;
+    a.mom = nullptr;
+    a.n_mom = 0;
+    a.stats_w = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     if (ctx().prof) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)

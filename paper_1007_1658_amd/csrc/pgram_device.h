@@ -109,6 +109,45 @@ __device__ __forceinline__ Moments block_merge_256(Moments v)
     return r;
 }
 
+// All partial moments merged in one fixed order, whatever the block size:
+// leaf i < 256 folds parts i, i + 256, ..., then a 256-leaf tree (the block's
+// threads take the leaves and the tree's nodes in turn).  Every block that
+// calls it gets the same bits.
+__device__ __forceinline__ Moments merge_parts(const Moments *__restrict__ part, int n_part)
+{
+    __shared__ Moments sm[256];
+    const int tid = threadIdx.x;
+    for (int l = tid; l < 256; l += blockDim.x) {
+        Moments m = moments_empty();
+        for (int i = l; i < n_part; i += 256) m = moments_merge(m, part[i]);
+        sm[l] = m;
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        for (int l = tid; l < w; l += blockDim.x) sm[l] = moments_merge(sm[l], sm[l + w]);
+        __syncthreads();
+    }
+    Moments r = sm[0];
+    __syncthreads();
+    return r;
+}
+
+// the curve's scalars from its merged moments
+__device__ __forceinline__ CurveStats stats_of(const Moments &m, int phase)
+{
+    CurveStats s;
+    s.mean = m.mean;
+    s.var = m.m2 / m.n;
+    s.zero_var = (m.m2 > 0.0) ? 0 : 1;
+    s.inv_var = s.zero_var ? 0.0 : 1.0 / s.var;
+    s.t_min = m.tmin;
+    s.t_max = m.tmax;
+    s.wsum = m.n;
+    s.t_ref = (phase == PH_NAIVE) ? 0.0 : 0.5 * (m.tmin + m.tmax);
+    s.pad_ = 0;
+    return s;
+}
+
 // one sample's record: split time, centred value, recurrence step (cos, sin)
 __device__ __forceinline__ void write_record(const Records &rec, int64_t j, double tj, float xj,
                                              const CurveStats &s, double step_df, int phase)

@@ -38,30 +38,6 @@ __global__ void __launch_bounds__(256) prep_moments_kernel(const double *__restr
     if (threadIdx.x == 0) out[blockIdx.x] = m;
 }
 
-// all partial moments merged in a fixed order (every caller gets the same bits)
-__device__ __forceinline__ Moments merge_parts(const Moments *__restrict__ part, int n_part)
-{
-    Moments m = moments_empty();
-    for (int i = threadIdx.x; i < n_part; i += 256) m = moments_merge(m, part[i]);
-    return block_merge_256(m);
-}
-
-// the curve's scalars from its merged moments
-__device__ __forceinline__ CurveStats stats_of(const Moments &m, int phase)
-{
-    CurveStats s;
-    s.mean = m.mean;
-    s.var = m.m2 / m.n;
-    s.zero_var = (m.m2 > 0.0) ? 0 : 1;
-    s.inv_var = s.zero_var ? 0.0 : 1.0 / s.var;
-    s.t_min = m.tmin;
-    s.t_max = m.tmax;
-    s.wsum = m.n;
-    s.t_ref = (phase == PH_NAIVE) ? 0.0 : 0.5 * (m.tmin + m.tmax);
-    s.pad_ = 0;
-    return s;
-}
-
 __global__ void __launch_bounds__(256) prep_finalize_kernel(const Moments *__restrict__ part, int n_part,
                                                             int phase, CurveStats *__restrict__ st)
 {
@@ -101,6 +77,15 @@ hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_
     hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
     hipLaunchKernelGGL(prep_records_kernel, dim3(record_blocks(Nt)), dim3(256), 0, s, t, x, Nt,
                        (const Moments *)moments, n_moment_blocks, stats, step_df, phase, rec);
+    return hipGetLastError();
+}
+
+// the partial moments alone: the matrix-core periodogram merges them and
+// converts the samples itself, so it needs no records
+hipError_t launch_moment_parts(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
     return hipGetLastError();
 }
 

@@ -483,14 +483,49 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
     const int64_t jb = (int64_t)split * a.chunk;
     const int64_t je = (jb + a.chunk < a.Nt) ? jb + a.chunk : a.Nt;
 
-    // chunk scale: 2^(14 - e) with max|value| < 2^e
-    float mx = 0.f;
-    for (int64_t j = jb + tid; j < je; j += blockDim.x) mx = fmaxf(mx, fabsf(a.rec.xv[j]));
-    mx = wave_max(mx);
-    if (lane == 0) S.red[0][wave] = mx;
+    // the chunk's range of raw values (before the curve's mean is known: the
+    // centred values' extremes are those of the raw ones, rounding being
+    // monotonic), and the first block's samples, loaded into registers one
+    // block ahead so that global-memory latency overlaps other work
+    float xlo = INFINITY, xhi = -INFINITY;
+    for (int64_t j = jb + tid; j < je; j += blockDim.x) {
+        const float v = a.x_raw[j];
+        xlo = fminf(xlo, v);
+        xhi = fmaxf(xhi, v);
+    }
+    double pt = 0.0;
+    float px = 0.f;
+    bool pok = false;
+    if (tid < kMB) {
+        const int64_t j = jb + tid;
+        pok = j < je;
+        if (pok) {
+            pt = a.t_raw[j];
+            px = a.x_raw[j];
+        }
+    }
+    // the curve's mean and time reference, merged from the prep's partial
+    // moments in the record kernel's order (the same bits in every workgroup)
+    const CurveStats cs = stats_of(merge_parts(a.mom, a.n_mom), (int)PH_SPLIT);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.stats_w = cs;
+
+    // chunk scale: 2^(14 - e) with max|x - mean| < 2^e, the centred values
+    // rounded to FP32 as the records hold them
+    xlo = -wave_max(-xlo);
+    xhi = wave_max(xhi);
+    if (lane == 0) {
+        S.red[0][wave] = xhi;
+        S.red[1][wave] = xlo;
+    }
     __syncthreads();
-    mx = S.red[0][0];
-    for (int w = 1; w < nw; ++w) mx = fmaxf(mx, S.red[0][w]);
+    xhi = S.red[0][0];
+    xlo = S.red[1][0];
+    for (int w = 1; w < nw; ++w) {
+        xhi = fmaxf(xhi, S.red[0][w]);
+        xlo = fminf(xlo, S.red[1][w]);
+    }
+    const float mx = (xlo <= xhi) ? fmaxf(fabsf((float)((double)xhi - cs.mean)), fabsf((float)((double)xlo - cs.mean)))
+                                  : 0.0f;
     int ex = 0;
     (void)frexpf(mx, &ex);
     const float xscale = ldexpf(1.0f, 14 - ex);
@@ -503,34 +538,24 @@ __device__ __forceinline__ void mfma_sums_pm(const PgramArgs &a)
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = floatx16{};
 
-    // the next block's samples, loaded into registers one block ahead so that
-    // the global-memory latency overlaps the current block's products
-    float pth = 0.f, ptl = 0.f, pxv = 0.f;
-    bool pok = false;
-    if (tid < kMB) {
-        const int64_t j = jb + tid;
-        pok = j < je;
-        if (pok) {
-            pth = a.rec.th[j];
-            ptl = a.rec.tl[j];
-            pxv = a.rec.xv[j];
-        }
-    }
     for (int64_t j0 = jb; j0 < je; j0 += kMB) {
         __syncthreads();  // the previous block's LDS is consumed
         lds_poison(S);
         if (tid < kMB) {
-            // ragged end: neutral samples t' = 0, x = 0, and a double-angle
-            // scale of 0 so that they add nothing to CC
-            S.t[tid] = pok ? (double)pth + (double)ptl : 0.0;
-            S.x[tid] = pok ? pxv * xscale : 0.0f;
+            // t' = t - t_ref split into FP32 hi + lo and x - mean rounded to
+            // FP32, as the record kernel writes them; ragged end: neutral
+            // samples t' = 0, x = 0, and a double-angle scale of 0 so that
+            // they add nothing to CC
+            float th = 0.f, tl = 0.f;
+            if (pok) split_time(pt - cs.t_ref, th, tl);
+            S.t[tid] = pok ? (double)th + (double)tl : 0.0;
+            S.x[tid] = pok ? (float)((double)px - cs.mean) * xscale : 0.0f;
             S.w[tid] = pok ? kTrigScale : 0.0f;  // R2 of the pads: 0
             const int64_t j = j0 + kMB + tid;
             pok = j < je;
             if (pok) {
-                pth = a.rec.th[j];
-                ptl = a.rec.tl[j];
-                pxv = a.rec.xv[j];
+                pt = a.t_raw[j];
+                px = a.x_raw[j];
             }
         }
         __syncthreads();
