@@ -46,6 +46,26 @@ def test_c0_all_shapes(c0_case, phase, trig, m, unroll, summ, waves, splits):
     assert peak_matches(Pg, P)
 
 
+@pytest.mark.parametrize("waves", [1, 2, 4, 8])
+@pytest.mark.parametrize("Nt,Nf,splits", [(1000, 2000, 1), (1000, 2000, 7), (4097, 3001, 3), (300, 129, 2)])
+def test_matrix_core_every_workgroup_size(waves, Nt, Nf, splits):
+    """The matrix-core kernel merges the curve's partial moments inside every
+    workgroup (any of its 1-8 waves) and converts the raw samples itself:
+    parity at each workgroup size, on ragged sizes and a shifted epoch."""
+    print(f"mfma waves={waves} Nt={Nt} Nf={Nf} splits={splits}", flush=True)
+    g = np.random.default_rng([13, Nt, Nf, splits])
+    tt = np.sort(g.uniform(0.0, 40.0, Nt)) + 5.0e4
+    xx = (3.0 * np.sin(2 * np.pi * 0.7 * tt) + g.normal(0, 1.0, Nt) + 20.0).astype(np.float32)
+    df = 1.0 / (4.0 * (tt[-1] - tt[0]))
+    f_min = 0.5 * df
+    P = oracle.periodogram(tt, xx, f_min, df, Nf=Nf)
+    t = torch.from_numpy(tt).cuda()
+    x = torch.from_numpy(xx).cuda()
+    Pg = lsp.lsp_periodogram_ex(t, x, f_min, df, Nf, trig="mfma", m=32, waves=waves, splits=splits).cpu().numpy()
+    assert rel_err(Pg, P) <= REL_TOL
+    assert peak_matches(Pg, P)
+
+
 @pytest.mark.parametrize("Nt,Nf,splits", [
     (2, 1, 1), (3, 7, 1), (63, 100, 1), (64, 64, 1), (65, 513, 2), (130, 1025, 3),
     (1000, 511, 4), (4097, 3000, 5), (257, 8193, 1), (5000, 20, 64),
