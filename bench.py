@@ -118,36 +118,57 @@ def warm(fn, warmup, min_seconds=0.3):
     torch.cuda.synchronize()
 
 
-def time_steps(fn, steps, warmup, on_start=None, per_step=None):
-    """Seconds per step over exactly `steps` steps after `warmup` untimed ones.
-    per_step (a list) receives each step's own duration in ms, from events
-    recorded between the steps on the stream they run on (no host sync in
-    between, so they measure the same back-to-back run)."""
+def time_steps(fn, steps, warmup, on_start=None):
+    """Seconds per step over exactly `steps` steps after `warmup` untimed ones
+    (host clock, the stream synchronized on both sides; nothing is recorded
+    on the stream between the steps).  on_start runs after the warm-up, e.g.
+    to enable the library's profiling hook for the pass."""
     import torch
     warm(fn, warmup)
     if on_start:
         on_start()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)] if per_step is not None else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        if ev:
-            ev[i].record()
         fn()
-    if ev:
-        ev[steps].record()
     torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / steps
-    if ev:
-        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
-    return sec
+    return (time.perf_counter() - t0) / steps
 
 
-def step_stats(ms):
+KERNEL_TIMING = ("HIP events attached to the kernel's launches, in a second pass of the same steps "
+                 "(the value's pass records none)")
+
+
+def profiled_passes(fn, steps, calls=True):
+    """After the value's timed pass: one more pass of `steps` steps with the
+    main kernel's events (its average duration, symbol name) and, for
+    single-curve calls, one with each call's events (its device span).
+    Events attached to the launches add no commands to the stream but still
+    delay each call (about 5 us per pair on a c1 call), so every figure comes
+    from a pass that carries only its own events."""
+    import paper_1007_1658_amd as lsp
+    time_steps(fn, steps, 0, on_start=lambda: lsp.lsp_profile_enable(lsp.PROFILE_KERNEL))
+    k_ms, k_n, k_name = lsp.lsp_profile_read()
+    span = None
+    if calls:
+        time_steps(fn, steps, 0, on_start=lambda: lsp.lsp_profile_enable(lsp.PROFILE_CALLS))
+        span = lsp.lsp_profile_read_calls()
+    lsp.lsp_profile_enable(False)
+    return k_ms / 1e3 / max(k_n, 1), k_name, span
+
+
+def step_stats(ms, what=None):
     a = np.asarray(ms, dtype=np.float64)
-    return {"n": int(a.size), "median_ms": float(np.median(a)), "mean_ms": float(a.mean()),
-            "std_ms": float(a.std(ddof=1)) if a.size > 1 else 0.0,
-            "min_ms": float(a.min()), "max_ms": float(a.max())}
+    out = {"n": int(a.size), "median_ms": float(np.median(a)), "mean_ms": float(a.mean()),
+           "std_ms": float(a.std(ddof=1)) if a.size > 1 else 0.0,
+           "min_ms": float(a.min()), "max_ms": float(a.max())}
+    if what:
+        out["of"] = what
+    return out
+
+
+CALL_TIME = ("device time of each call, its first kernel's start to its last kernel's end (HIP events on "
+             "those launches, in a third pass of the same steps)")
 
 
 def sampled_error(curve, Pg, n=256, seed=0):
@@ -338,10 +359,8 @@ def run_gls(args):
     else:
         P = oracle.gls(c.t, c.x.astype(np.float64), c.f_min, c.df, k=k, w=w.astype(np.float64))
     err = float(np.max(np.abs(pg[k] - P)) / P.max())
-    sec = time_steps(step, args.steps, args.warmup, on_start=lambda: lsp.lsp_profile_enable(True))
-    k_ms, k_n, k_name = lsp.lsp_profile_read()
-    lsp.lsp_profile_enable(False)
-    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    sec = time_steps(step, args.steps, args.warmup)
+    k_avg_s, k_name, _ = profiled_passes(step, args.steps, calls=False)
     terms = c.Nt * c.Nf
     flop = MH_FLOP_PER_TERM(K) if mh else GLS_FLOP_PER_TERM
     issued = ISSUED_FLOP_PER_HARMONIC * (K if mh else 1) // (2 if (mh or k_name == "gls_pm_kernel") else 1)
@@ -355,7 +374,8 @@ def run_gls(args):
         "max_rel_err": err, "meets_1e-4": bool(err <= REL_TOL),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP16_TFLOPS, "traffic": traffic_from_profiles(k_name, args.config),
-                     "kernel": k_name, "kernel_avg_ms": k_avg_s * 1e3, "flop_per_term": flop,
+                     "kernel": k_name, "kernel_avg_ms": k_avg_s * 1e3, "kernel_timing": KERNEL_TIMING,
+                     "flop_per_term": flop,
                      "mfma_issued": {"flop_per_term": issued,
                                      "frac": issued * terms / k_avg_s / 1e12 / PEAK_FP16_TFLOPS}},
     }
@@ -476,13 +496,10 @@ def main():
     torch.cuda.synchronize()
     err_split = sampled_error(curve, Pn.cpu().numpy())
 
-    # the profiling hook brackets the main kernel of the timed steps only
-    steps_ms = []
-    sec = time_steps(run_split, args.steps, args.warmup, on_start=lambda: lsp.lsp_profile_enable(True),
-                     per_step=steps_ms)
-    k_ms, k_n, k_name = lsp.lsp_profile_read()
-    lsp.lsp_profile_enable(False)
-    k_avg_s = k_ms / 1e3 / max(k_n, 1)
+    # the value's pass records nothing on the stream; the main kernel's
+    # duration and each call's span come from passes of the same steps
+    sec = time_steps(run_split, args.steps, args.warmup)
+    k_avg_s, k_name, steps_ms = profiled_passes(run_split, args.steps)
     terms = curve.Nt * curve.Nf
     value = terms / sec
 
@@ -512,19 +529,17 @@ def main():
         run_valu()
         torch.cuda.synchronize()
         err_v = sampled_error(curve, Pv.cpu().numpy())
-        v_ms = []
-        sec_v = time_steps(run_valu, max(20, args.steps // 2), 2, on_start=lambda: lsp.lsp_profile_enable(True),
-                           per_step=v_ms)
-        kv_ms, kv_n, kv_name = lsp.lsp_profile_read()
-        lsp.lsp_profile_enable(False)
-        kv_s = kv_ms / 1e3 / max(kv_n, 1)
+        v_steps = max(20, args.steps // 2)
+        sec_v = time_steps(run_valu, v_steps, 2)
+        kv_s, kv_name, v_ms = profiled_passes(run_valu, v_steps)
         ach_v = FLOP_PER_TERM * terms / kv_s / 1e12
-        valu = {"value": terms / sec_v, "ms_per_step": sec_v * 1e3, "step_stats": step_stats(v_ms),
+        valu = {"value": terms / sec_v, "ms_per_step": sec_v * 1e3, "step_stats": step_stats(v_ms, CALL_TIME),
                 "kernel": kv_name, "kernel_avg_ms": kv_s * 1e3,
                 "frac_fp32_valu_peak": ach_v / PEAK_FP32_TFLOPS,
                 "frac_fp32_valu_peak_whole_call": FLOP_PER_TERM * terms / sec_v / 1e12 / PEAK_FP32_TFLOPS,
                 "roofline": {"bound": "alu", "achieved": ach_v, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                              "frac": ach_v / PEAK_FP32_TFLOPS, "flop_per_term": FLOP_PER_TERM,
+                             "kernel_timing": KERNEL_TIMING,
                              "traffic": traffic_from_profiles(kv_name, args.config)},
                 "max_rel_err": err_v, "meets_1e-4": bool(err_v <= REL_TOL)}
 
@@ -561,6 +576,7 @@ def main():
         "traffic": traffic,
         "kernel": k_name,
         "kernel_avg_ms": k_avg_s * 1e3,
+        "kernel_timing": KERNEL_TIMING,
         "flop_per_term": FLOP_PER_TERM,
     }
     if mfma:
@@ -576,7 +592,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": sec * 1e3,
-        "step_stats": step_stats(steps_ms),
+        "step_stats": step_stats(steps_ms, CALL_TIME),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

@@ -500,14 +500,30 @@ lsp_status lsp_probe_cpair(const float *L, const float *R, int32_t K, float *Pp,
 
 /* ---- profiling hook ------------------------------------------------------------
 
-   While enabled, every launch of the main periodogram kernel is bracketed
-   by HIP events recorded on the stream it runs on.  lsp_profile_read
-   synchronizes those events and returns the total kernel time (ms), the
-   number of launches and the kernel's symbol name (truncated to name_len).
-   Enabling clears previous records. */
+   on: 0 = off; bit 0 (1) = every launch of the main periodogram kernel
+   carries HIP events for its start and end (of the first and last pass
+   where the generalized or multi-harmonic periodogram makes several);
+   bit 1 (2) = every single-curve call (lsp_periodogram, _ex, _noalloc)
+   carries events on its first kernel's start and its last kernel's end.
+   The extended launch takes the events from the dispatches themselves, so
+   the stream gets no marker commands; still, on MI355X the main kernel's
+   pair delays a c1-sized call by about 5 us and the call pair by about 6 us
+   more.  Enabling (or disabling) clears previous records.
+
+   lsp_profile_read synchronizes the main kernel's events and returns the
+   total kernel time (ms), the number of launches and the kernel's symbol
+   name (truncated to name_len).
+
+   lsp_profile_read_calls: the device time of each recorded call, in call
+   order, from the start of its first kernel to the end of its last one.
+   Writes min(cap, calls) values to the host array ms (ms may be NULL when
+   cap = 0) and the number of calls recorded to *calls.  Synchronizes the
+   events it reads.  LSP_ERR_INVALID_ARG for cap < 0 or a NULL ms with
+   cap > 0. */
 lsp_status lsp_profile_enable(int32_t on);
 lsp_status lsp_profile_read(double *total_ms, int64_t *launches, char *name,
                             int32_t name_len);
+lsp_status lsp_profile_read_calls(double *ms, int64_t cap, int64_t *calls);
 
 /* ---- host-only helpers (no GPU needed) -------------------------------------------
 

@@ -115,6 +115,7 @@ SIGNATURES = {
     "lsp_probe_cpair": (_I32, [_P, _P, _I32, _P, _P, _P]),
     "lsp_profile_enable": (_I32, [_I32]),
     "lsp_profile_read": (_I32, [ctypes.POINTER(_D), ctypes.POINTER(_I64), ctypes.c_char_p, _I32]),
+    "lsp_profile_read_calls": (_I32, [_P, _I64, ctypes.POINTER(_I64)]),
     "lsp_grid_paper": (_I32, [_D, _D, _I64, _D, _D, _I32, ctypes.POINTER(_D), ctypes.POINTER(_D),
                               ctypes.POINTER(_I64)]),
     "lsp_fap_analytic": (_D, [_D, _I64, _I64]),
@@ -568,8 +569,14 @@ def lsp_probe_cpair(L, R, stream=None):
     return Pp, Pm
 
 
-def lsp_profile_enable(on: bool = True):
-    _check(lib().lsp_profile_enable(1 if on else 0), "lsp_profile_enable")
+PROFILE_KERNEL = 1   # events on the main kernel's launches
+PROFILE_CALLS = 2    # events on each single-curve call's first and last kernels
+
+
+def lsp_profile_enable(on=True):
+    """on: False/0 off, True = PROFILE_KERNEL, or a mask of PROFILE_KERNEL | PROFILE_CALLS."""
+    mode = PROFILE_KERNEL if on is True else int(on)
+    _check(lib().lsp_profile_enable(mode), "lsp_profile_enable")
 
 
 def lsp_profile_read():
@@ -578,6 +585,16 @@ def lsp_profile_read():
     buf = ctypes.create_string_buffer(256)
     _check(lib().lsp_profile_read(ctypes.byref(tot), ctypes.byref(n), buf, 256), "lsp_profile_read")
     return tot.value, int(n.value), buf.value.decode()
+
+
+def lsp_profile_read_calls():
+    """Device ms of each single-curve call since lsp_profile_enable (first kernel's start to last kernel's end)."""
+    n = _I64()
+    _check(lib().lsp_profile_read_calls(None, 0, ctypes.byref(n)), "lsp_profile_read_calls")
+    out = np.zeros(int(n.value), dtype=np.float64)
+    if out.size:
+        _check(lib().lsp_profile_read_calls(out.ctypes.data, out.size, ctypes.byref(n)), "lsp_profile_read_calls")
+    return out
 
 
 # ---- false-alarm surrogate ------------------------------------------------------------

@@ -132,9 +132,9 @@ struct BatchArgs {
 // ---- kernel launchers (pgram_kernels.hip) --------------------------------------
 hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_df,
                        int phase, Moments *moments, int n_moment_blocks,
-                       CurveStats *stats, Records rec, hipStream_t s);
+                       CurveStats *stats, Records rec, hipStream_t s, hipEvent_t call_start = nullptr);
 hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hipStream_t s,
-                        hipEvent_t ev0, hipEvent_t ev1);
+                        hipEvent_t ev0, hipEvent_t ev1, hipEvent_t call_end = nullptr);
 const char *pgram_kernel_name(int phase, const lsp_tile &tile);
 bool pgram_tile_supported(int phase, const lsp_tile &tile);
 void pgram_complete_tile(int phase, lsp_tile &tile);
@@ -163,7 +163,7 @@ hipError_t launch_refine(const PgramArgs &a, int K, hipStream_t s);
 
 // moments and CurveStats only (no records)
 hipError_t launch_moment_parts(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
-                               hipStream_t s);
+                               hipStream_t s, hipEvent_t call_start = nullptr);
 hipError_t launch_moments(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
                           CurveStats *stats, hipStream_t s);
 // extirpolation + FFT periodogram (fast_kernels.hip): grids = 2 N doubles (values, ones at 2u);

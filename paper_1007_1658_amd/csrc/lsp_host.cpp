@@ -64,8 +64,9 @@ struct Context {
     std::mutex mu;
     std::map<int, DeviceInfo> dev;
     std::map<std::pair<int, hipStream_t>, std::unique_ptr<StreamCtx>> streams;
-    bool prof = false;
+    int prof = 0;  // profiling hook: bit 0 the main kernel's events, bit 1 per-call events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_calls;  // single-curve calls: first kernel .. last kernel
     std::string prof_name;
 };
 
@@ -355,10 +356,24 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     // the matrix-core kernel merges the partial moments and converts the raw
     // samples itself; the other forms read records (the step rotations serve
     // the recurrence form)
+    // profiling hook: events on the main kernel, and on the call's first and
+    // last kernels (the whole call), all attached to the launches themselves
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, call0 = nullptr, call1 = nullptr;
+    if (allow_profile && (ctx().prof & 1)) {
+        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
+            return hip_fail(hipGetLastError(), "hipEventCreate");
+        ctx().prof_events.emplace_back(ev0, ev1);
+        ctx().prof_name = pgram_kernel_name(phase, tile);
+    }
+    if (allow_profile && (ctx().prof & 2)) {
+        if (hipEventCreate(&call0) != hipSuccess || hipEventCreate(&call1) != hipSuccess)
+            return hip_fail(hipGetLastError(), "hipEventCreate");
+        ctx().prof_calls.emplace_back(call0, call1);
+    }
     Moments *moments = (Moments *)(base + L.moments);
     const bool mfma = tile.trig == LSP_TRIG_MFMA;
-    hipError_t e = mfma ? launch_moment_parts(t, x, Nt, moments, n_mom, s)
-                        : launch_prep(t, x, Nt, (double)kWave * df, phase, moments, n_mom, stats, rec, s);
+    hipError_t e = mfma ? launch_moment_parts(t, x, Nt, moments, n_mom, s, call0)
+                        : launch_prep(t, x, Nt, (double)kWave * df, phase, moments, n_mom, stats, rec, s, call0);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
 
     PgramArgs a;
@@ -381,14 +396,7 @@ static lsp_status run_single(const double *t, const float *x, int64_t Nt, double
     a.n_mom = n_mom;
     a.stats_w = stats;
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (allow_profile && ctx().prof) {
-        if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
-            return hip_fail(hipGetLastError(), "hipEventCreate");
-        ctx().prof_events.emplace_back(ev0, ev1);
-        ctx().prof_name = pgram_kernel_name(phase, tile);
-    }
-    e = launch_pgram(a, phase, tile, s, ev0, ev1);
+    e = launch_pgram(a, phase, tile, s, ev0, ev1, call1);
     if (e != hipSuccess) return hip_fail(e, "periodogram launch");
     if (stats_out) *stats_out = stats;
     return LSP_OK;
@@ -965,7 +973,7 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
     a.n_mom = 0;
     a.stats_w = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (ctx().prof) {
+    if (ctx().prof & 1) {
         if (hipEventCreate(&ev0) != hipSuccess || hipEventCreate(&ev1) != hipSuccess)
             return hip_fail(hipGetLastError(), "hipEventCreate");
         ctx().prof_events.emplace_back(ev0, ev1);
@@ -1154,13 +1162,15 @@ lsp_status lsp_probe_recurrence(const double *t, int64_t n, double t_ref, double
 lsp_status lsp_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lock(ctx().mu);
-    for (auto &p : ctx().prof_events) {
-        hipEventDestroy(p.first);
-        hipEventDestroy(p.second);
+    for (auto *v : {&ctx().prof_events, &ctx().prof_calls}) {
+        for (auto &p : *v) {
+            hipEventDestroy(p.first);
+            hipEventDestroy(p.second);
+        }
+        v->clear();
     }
-    ctx().prof_events.clear();
     ctx().prof_name.clear();
-    ctx().prof = on != 0;
+    ctx().prof = on & 3;
     return LSP_OK;
 }
 
@@ -1182,6 +1192,26 @@ lsp_status lsp_profile_read(double *total_ms, int64_t *launches, char *name, int
         std::strncpy(name, ctx().prof_name.c_str(), (size_t)name_len - 1);
         name[name_len - 1] = 0;
     }
+    return LSP_OK;
+}
+
+lsp_status lsp_profile_read_calls(double *ms, int64_t cap, int64_t *calls)
+{
+    if (cap < 0 || (cap > 0 && !ms)) {
+        g_last_error = "ms must hold cap values";
+        return LSP_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(ctx().mu);
+    const auto &v = ctx().prof_calls;
+    for (size_t i = 0; i < v.size() && (int64_t)i < cap; ++i) {
+        hipError_t e = hipEventSynchronize(v[i].second);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.f;
+        e = hipEventElapsedTime(&t, v[i].first, v[i].second);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        ms[i] = t;
+    }
+    if (calls) *calls = (int64_t)v.size();
     return LSP_OK;
 }
 

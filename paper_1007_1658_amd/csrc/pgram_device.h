@@ -6,9 +6,25 @@
 
 #include <math.h>
 
+#include <hip/hip_ext.h>
+
 #include "internal.h"
 
 namespace lsp {
+
+// A launch that, while the profiling hook is on, carries HIP events for its
+// own start and end: the extended launch takes them from the dispatch itself,
+// so the stream gets no marker commands between kernels (on MI355X a
+// recorded event holds the stream for about 5 us).  No events: a plain launch.
+template <typename... KArgs, typename... Args>
+static inline void launch_timed(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, hipEvent_t start,
+                                hipEvent_t stop, Args... args)
+{
+    if (start || stop)
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, start, stop, 0u, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 enum { PH_SPLIT = LSP_PHASE_SPLIT, PH_NAIVE = LSP_PHASE_NAIVE, PH_SPLIT32 = LSP_PHASE_SPLIT32 };
 enum { TR_DIRECT = LSP_TRIG_DIRECT, TR_RECUR = LSP_TRIG_RECUR, TR_MFMA = LSP_TRIG_MFMA };

@@ -72,9 +72,9 @@ static unsigned record_blocks(int64_t Nt)
 
 hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_df, int phase,
                        Moments *moments, int n_moment_blocks, CurveStats *stats, Records rec,
-                       hipStream_t s)
+                       hipStream_t s, hipEvent_t call_start)
 {
-    hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
+    launch_timed(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), s, call_start, nullptr, t, x, Nt, moments);
     hipLaunchKernelGGL(prep_records_kernel, dim3(record_blocks(Nt)), dim3(256), 0, s, t, x, Nt,
                        (const Moments *)moments, n_moment_blocks, stats, step_df, phase, rec);
     return hipGetLastError();
@@ -83,9 +83,9 @@ hipError_t launch_prep(const double *t, const float *x, int64_t Nt, double step_
 // the partial moments alone: the matrix-core periodogram merges them and
 // converts the samples itself, so it needs no records
 hipError_t launch_moment_parts(const double *t, const float *x, int64_t Nt, Moments *moments, int n_moment_blocks,
-                               hipStream_t s)
+                               hipStream_t s, hipEvent_t call_start)
 {
-    hipLaunchKernelGGL(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), 0, s, t, x, Nt, moments);
+    launch_timed(prep_moments_kernel, dim3(n_moment_blocks), dim3(256), s, call_start, nullptr, t, x, Nt, moments);
     return hipGetLastError();
 }
 
@@ -294,23 +294,20 @@ hipError_t pgram_occupancy(int phase, const lsp_tile &tile, int *blocks_per_cu)
 }
 
 hipError_t launch_pgram(const PgramArgs &a, int phase, const lsp_tile &tile, hipStream_t s,
-                        hipEvent_t ev0, hipEvent_t ev1)
+                        hipEvent_t ev0, hipEvent_t ev1, hipEvent_t call_end)
 {
     const Variant *v = find_variant(phase, tile);
     if (!v) return hipErrorInvalidValue;
     const int64_t per_wave = (int64_t)kWave * tile.m;
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + tile.waves - 1) / tile.waves;
-    if (ev0) hipEventRecord(ev0, s);
-    hipLaunchKernelGGL(v->fn, dim3((unsigned)nblk, (unsigned)tile.splits), dim3(kWave * tile.waves), 0,
-                       s, a);
-    if (ev1) hipEventRecord(ev1, s);
+    launch_timed(v->fn, dim3((unsigned)nblk, (unsigned)tile.splits), dim3(kWave * tile.waves), s, ev0, ev1, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int64_t nb = (a.Nf + 255) / 256;
     const int64_t pads = (tile.trig == TR_MFMA) ? 0 : pad_count(a.Nt);
-    hipLaunchKernelGGL(pgram_reduce_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const float *)a.part,
-                       tile.splits, a.Nf, a.Nt, pads, a.stats, a.Pn);
+    launch_timed(pgram_reduce_kernel, dim3((unsigned)nb), dim3(256), s, nullptr, call_end, (const float *)a.part,
+                 (int)tile.splits, a.Nf, a.Nt, pads, (const CurveStats *)a.stats, a.Pn);
     return hipGetLastError();
 }
 

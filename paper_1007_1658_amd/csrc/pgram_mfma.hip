@@ -1113,12 +1113,8 @@ hipError_t launch_gls(const PgramArgs &a, int waves, hipStream_t s, hipEvent_t e
     const int64_t per_wave = pm ? kGlsPmFreqPerWave : kGlsFreqPerWave;
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + waves - 1) / waves;
-    if (ev0) hipEventRecord(ev0, s);
-    if (pm)
-        hipLaunchKernelGGL(gls_pm_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
-    else
-        hipLaunchKernelGGL(gls_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves), 0, s, a);
-    if (ev1) hipEventRecord(ev1, s);
+    launch_timed(pm ? gls_pm_kernel : gls_mfma_kernel, dim3((unsigned)nblk, (unsigned)a.splits), dim3(kWave * waves),
+                 s, ev0, ev1, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(gls_reduce_kernel, dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,
@@ -1663,24 +1659,23 @@ static hipError_t launch_mh_k(const PgramArgs &a, int waves, hipStream_t s, hipE
     const int64_t nfb = (a.Nf + per_wave - 1) / per_wave;
     const int64_t nblk = (nfb + waves - 1) / waves;
     const dim3 grid((unsigned)nblk, (unsigned)a.splits), block(kWave * waves);
-    if (ev0) hipEventRecord(ev0, s);
     // passes of at most three complex sums: weight harmonics 1..2K, then the
-    // value harmonics 1..K
+    // value harmonics 1..K; the hook's events span the first pass's start to
+    // the last pass's end
     if constexpr (K == 2) {
-        hipLaunchKernelGGL((mh_mfma_kernel<2, 1, 3, 1, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<2, 4, 4, 1, 2>), grid, block, 0, s, a);
+        launch_timed(mh_mfma_kernel<2, 1, 3, 1, 0>, grid, block, s, ev0, nullptr, a);
+        launch_timed(mh_mfma_kernel<2, 4, 4, 1, 2>, grid, block, s, nullptr, ev1, a);
     } else if constexpr (K == 3) {
-        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 3, 1, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<3, 4, 6, 1, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<3, 1, 0, 1, 3>), grid, block, 0, s, a);
+        launch_timed(mh_mfma_kernel<3, 1, 3, 1, 0>, grid, block, s, ev0, nullptr, a);
+        launch_timed(mh_mfma_kernel<3, 4, 6, 1, 0>, grid, block, s, nullptr, nullptr, a);
+        launch_timed(mh_mfma_kernel<3, 1, 0, 1, 3>, grid, block, s, nullptr, ev1, a);
     } else {
         static_assert(K == 4, "K = 2, 3 or 4");
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 3, 1, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 4, 6, 1, 0>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 7, 8, 1, 1>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((mh_mfma_kernel<4, 1, 0, 2, 4>), grid, block, 0, s, a);
+        launch_timed(mh_mfma_kernel<4, 1, 3, 1, 0>, grid, block, s, ev0, nullptr, a);
+        launch_timed(mh_mfma_kernel<4, 4, 6, 1, 0>, grid, block, s, nullptr, nullptr, a);
+        launch_timed(mh_mfma_kernel<4, 7, 8, 1, 1>, grid, block, s, nullptr, nullptr, a);
+        launch_timed(mh_mfma_kernel<4, 1, 0, 2, 4>, grid, block, s, nullptr, ev1, a);
     }
-    if (ev1) hipEventRecord(ev1, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((mh_reduce_kernel<K>), dim3((unsigned)((a.Nf + 255) / 256)), dim3(256), 0, s,

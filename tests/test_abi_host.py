@@ -100,7 +100,7 @@ def test_validation_happens_before_any_gpu_work():
         lsp.LSP_ERR_UNSUPPORTED
 
 
-def test_probe_validation_on_host():
+def test_matrix_core_probe_validation_on_host():
     L = lsp.lib()
     null = ctypes.c_void_p(0)
     fake = ctypes.c_void_p(16)
@@ -189,6 +189,15 @@ def test_fast_periodogram_validation_on_host():
     ]
     for c in cases:
         assert L.lsp_periodogram_fast(*c, null) == lsp.LSP_ERR_INVALID_ARG, c
+
+
+def test_profile_call_read_validation_on_host():
+    L = lsp.lib()
+    n = ctypes.c_int64(-1)
+    assert L.lsp_profile_read_calls(None, -1, ctypes.byref(n)) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_profile_read_calls(None, 4, ctypes.byref(n)) == lsp.LSP_ERR_INVALID_ARG
+    assert L.lsp_profile_enable(0) == lsp.LSP_OK
+    assert L.lsp_profile_read_calls(None, 0, ctypes.byref(n)) == lsp.LSP_OK and n.value == 0
 
 
 def test_microbench_validation_on_host():

@@ -237,12 +237,40 @@ def test_zero_frequency_and_constant_series():
 def test_profile_hook_counts_launches():
     c = synth.c0()
     t, x = to_dev(c)
-    lsp.lsp_profile_enable(True)
+    lsp.lsp_profile_enable(lsp.PROFILE_KERNEL | lsp.PROFILE_CALLS)
     for _ in range(3):
         lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf)
     ms, n, name = lsp.lsp_profile_read()
+    calls = lsp.lsp_profile_read_calls()
     lsp.lsp_profile_enable(False)
     assert n == 3 and ms > 0 and name.startswith(("pgram_kernel<", "pgram_mfma_kernel<"))
+    # each call's span (first kernel's start to last kernel's end) holds its main kernel
+    assert calls.shape == (3,) and np.all(calls > 0) and calls.sum() >= ms
+    assert lsp.lsp_profile_read_calls().size == 0   # disabling clears the records
+    lsp.lsp_profile_enable(lsp.PROFILE_CALLS)        # calls alone: no kernel records
+    lsp.lsp_periodogram(t, x, c.f_min, c.df, c.Nf)
+    ms, n, name = lsp.lsp_profile_read()
+    calls = lsp.lsp_profile_read_calls()
+    lsp.lsp_profile_enable(False)
+    assert n == 0 and calls.size == 1 and calls[0] > 0
+
+
+@pytest.mark.parametrize("K", [1, 3])
+def test_profile_hook_on_weighted_passes(K):
+    """The hook's events on the generalized (one launch) and multi-harmonic
+    (first pass's start to last pass's end) kernels."""
+    c = synth.c0()
+    t, x = to_dev(c)
+    lsp.lsp_profile_enable(True)
+    if K == 1:
+        lsp.lsp_gls(t, x, c.f_min, c.df, c.Nf)
+    else:
+        lsp.lsp_multiharmonic(t, x, K, c.f_min, c.df, c.Nf)
+    ms, n, name = lsp.lsp_profile_read()
+    calls = lsp.lsp_profile_read_calls()
+    lsp.lsp_profile_enable(False)
+    assert n == 1 and ms > 0 and name.startswith("gls_" if K == 1 else "mh_mfma_kernel")
+    assert calls.size == 0   # per-call spans are recorded for single-curve calls only
 
 
 def test_autotune_and_cache_roundtrip(tmp_path):
