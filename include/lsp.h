@@ -503,8 +503,9 @@ lsp_status lsp_probe_cpair(const float *L, const float *R, int32_t K, float *Pp,
    on: 0 = off; bit 0 (1) = every launch of the main periodogram kernel
    carries HIP events for its start and end (of the first and last pass
    where the generalized or multi-harmonic periodogram makes several);
-   bit 1 (2) = every single-curve call (lsp_periodogram, _ex, _noalloc)
-   carries events on its first kernel's start and its last kernel's end.
+   bit 1 (2) = every lsp_periodogram / lsp_periodogram_ex call carries
+   events on its first kernel's start and its last kernel's end.
+   lsp_periodogram_noalloc is never profiled (creating events allocates).
    The extended launch takes the events from the dispatches themselves, so
    the stream gets no marker commands; still, on MI355X the main kernel's
    pair delays a c1-sized call by about 5 us and the call pair by about 6 us
