@@ -529,7 +529,7 @@ def main():
         run_valu()
         torch.cuda.synchronize()
         err_v = sampled_error(curve, Pv.cpu().numpy())
-        v_steps = max(20, args.steps // 2)
+        v_steps = max(40, args.steps)
         sec_v = time_steps(run_valu, v_steps, 2)
         kv_s, kv_name, v_ms = profiled_passes(run_valu, v_steps)
         ach_v = FLOP_PER_TERM * terms / kv_s / 1e12
