@@ -208,7 +208,7 @@ int moment_blocks(int64_t Nt) { return (int)std::min<int64_t>(256, std::max<int6
 // occupancy of the variant; the cost model counts dispatch rounds times the
 // samples per wave (plus a fixed per-wave overhead), so that the last round is
 // not a nearly empty one.  blocks_per_cu <= 0: assume two workgroups per CU.
-int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus, int waves, int blocks_per_cu)
+int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus, int waves, int blocks_per_cu, int sums_per_freq)
 {
     if (waves < 1) waves = 4;
     if (blocks_per_cu <= 0) blocks_per_cu = 2;
@@ -222,8 +222,9 @@ int heuristic_splits(int64_t Nt, int64_t Nf, int m, int cus, int waves, int bloc
     // and Nt 12,000 14 % slower (its per-workgroup overheads and chunk sums)
     const int64_t min_chunk = (Nt <= 8192) ? kTile : 256;
     int64_t smax = std::max<int64_t>(1, std::min<int64_t>(256, (Nt + min_chunk - 1) / min_chunk));
-    // keep the per-chunk partial sums under 1 GiB
-    while (smax > 1 && (double)smax * 16.0 * (double)Nf > (double)(1u << 30)) --smax;
+    // keep the per-chunk partial sums (FP32, sums_per_freq per frequency) under 1 GiB
+    const double bytes_per_split = 4.0 * (double)std::max(1, sums_per_freq) * (double)Nf;
+    while (smax > 1 && (double)smax * bytes_per_split > (double)(1u << 30)) --smax;
     int64_t best_s = 1;
     double best_cost = 1e300;
     for (int64_t s = 1; s <= smax; ++s) {
@@ -918,7 +919,8 @@ static lsp_status run_weighted(const double *t, const float *y, const float *w, 
         // complex products, 32 per a-row)
         const bool pm = waves <= 4;
         const int per_wave = (K == 1) ? (pm ? kGlsPmFreqPerWave : kGlsFreqPerWave) : kMhFreqPerWave;
-        splits = heuristic_splits(Nt, Nf, per_wave / kWave, di->cus, waves, pm ? 4 / waves : 2);
+        splits = heuristic_splits(Nt, Nf, per_wave / kWave, di->cus, waves, pm ? 4 / waves : 2,
+                                  (K == 1) ? 6 : 6 * K);
     }
     int64_t chunk = 0;
     int eff = 1;
